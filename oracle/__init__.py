@@ -1,0 +1,174 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes wrapper of the plain FP64 CPU FEAST oracle
+(feast_oracle.c).  Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package; the GPU product never does.
+
+Arrays are numpy, column-major (Fortran order).  dtype "r64" = real symmetric A / real X,
+"c128" = complex Hermitian A / complex X.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libfeast_oracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force=False):
+    """Compile the oracle with the host C compiler (no GPU code involved)."""
+    src = os.path.join(_HERE, "feast_oracle.c")
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-fcx-fortran-rules", "-std=c11",
+               "-D_DEFAULT_SOURCE", "-Wall", src, "-o", _SO + ".tmp", "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        L.or_gauss_legendre.argtypes = [ctypes.c_int, _dp, _dp]
+        L.or_contour.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp]
+        L.or_zlu.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _ip]
+        L.or_zlu_solve.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _ip, ctypes.c_int, _dp,
+                                   ctypes.c_int, ctypes.c_int]
+        L.or_jacobi_eigh.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int]
+        L.or_filter_apply.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp,
+                                      ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int]
+        L.or_rayleigh_ritz.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, _dp, _dp, _ip]
+        L.or_feast_solve.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_double, _dp, ctypes.c_int, _dp, ctypes.c_int,
+                                     _dp, _dp, _ip, _ip, _dp]
+        L.or_num_threads.restype = ctypes.c_int
+        L.or_set_num_threads.argtypes = [ctypes.c_int]
+        L.or_set_fault.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _dt(dtype):
+    return {"r64": 0, "c128": 1}[dtype]
+
+
+def _fort(a, dtype):
+    want = np.complex128 if dtype == "c128" else np.float64
+    return np.asfortranarray(np.asarray(a, dtype=want))
+
+
+def set_fault(code: int):
+    """Plant a known mistake in the oracle (0 = none); for the mutation tests of the pins."""
+    lib().or_set_fault(int(code))
+
+
+def num_threads() -> int:
+    return lib().or_num_threads()
+
+
+def set_num_threads(n: int):
+    lib().or_set_num_threads(int(n))
+
+
+def gauss_legendre(n):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    st = lib().or_gauss_legendre(n, _ptr(x), _ptr(w))
+    if st:
+        raise ValueError(st)
+    return x, w
+
+
+def contour(emin, emax, nc):
+    z = np.zeros(2 * nc)
+    om = np.zeros(2 * nc)
+    st = lib().or_contour(emin, emax, nc, _ptr(z), _ptr(om))
+    if st:
+        raise ValueError(st)
+    return z.view(np.complex128), om.view(np.complex128)
+
+
+def zlu(M):
+    M = _fort(M, "c128").copy(order="F")
+    n = M.shape[0]
+    piv = np.zeros(n, dtype=np.int32)
+    st = lib().or_zlu(n, _ptr(M), n, piv.ctypes.data_as(_ip))
+    return M, piv, st
+
+
+def zlu_solve(LU, piv, B, adjoint=False):
+    B = _fort(B, "c128").copy(order="F")
+    n = LU.shape[0]
+    nrhs = B.shape[1]
+    LU = _fort(LU, "c128")
+    piv = np.ascontiguousarray(piv, dtype=np.int32)
+    lib().or_zlu_solve(n, _ptr(LU), n, piv.ctypes.data_as(_ip), nrhs, _ptr(B), n, int(adjoint))
+    return B
+
+
+def jacobi_eigh(H):
+    H = _fort(H, "c128").copy(order="F")
+    n = H.shape[0]
+    d = np.zeros(n)
+    V = np.zeros((n, n), dtype=np.complex128, order="F")
+    sweeps = lib().or_jacobi_eigh(n, _ptr(H), n, _ptr(d), _ptr(V), n)
+    return d, V, sweeps
+
+
+def filter_apply(dtype, A, emin, emax, nc, X):
+    A = _fort(A, dtype)
+    X = _fort(X, dtype)
+    n, m0 = X.shape
+    Q = np.zeros((n, m0), dtype=A.dtype, order="F")
+    st = lib().or_filter_apply(_dt(dtype), n, _ptr(A), n, emin, emax, nc, _ptr(X), n, m0,
+                               _ptr(Q), n)
+    if st:
+        raise RuntimeError(f"oracle filter_apply status {st}")
+    return Q
+
+
+def rayleigh_ritz(dtype, A, Q, emin, emax, anorm):
+    A = _fort(A, dtype)
+    Q = _fort(Q, dtype).copy(order="F")
+    n, m0 = Q.shape
+    lam = np.zeros(m0)
+    res = np.zeros(m0)
+    m = ctypes.c_int(0)
+    st = lib().or_rayleigh_ritz(_dt(dtype), n, _ptr(A), n, _ptr(Q), n, m0, emin, emax, anorm,
+                                _ptr(lam), _ptr(res), ctypes.byref(m))
+    return dict(status=st, X=Q, lam=lam, res=res, m=m.value)
+
+
+def feast_solve(dtype, A, emin, emax, nc, m0, tol, max_iter, anorm, X0):
+    A = _fort(A, dtype)
+    X0 = _fort(X0, dtype)
+    n = A.shape[0]
+    X = np.zeros((n, m0), dtype=A.dtype, order="F")
+    lam = np.zeros(m0)
+    res = np.zeros(m0)
+    m = ctypes.c_int(0)
+    iters = ctypes.c_int(0)
+    trace = np.zeros(max_iter)
+    st = lib().or_feast_solve(_dt(dtype), n, _ptr(A), n, emin, emax, nc, m0, tol, max_iter,
+                              anorm, _ptr(X0), n, _ptr(X), n, _ptr(lam), _ptr(res),
+                              ctypes.byref(m), ctypes.byref(iters), _ptr(trace))
+    return dict(status=st, X=X, lam=lam, res=res, m=m.value, iters=iters.value,
+                trace=trace[: iters.value])
