@@ -1,0 +1,150 @@
+/* feast.h -- C-ABI of the MI355X FEAST hot path (libfeast_mi355x.so, gfx950).
+ *
+ * FEAST (Gavin & Polizzi, "Enhancing the Performance and Robustness of the FEAST
+ * Eigensolver", arXiv 1605.08771) finds the eigenpairs (lambda, x) of a Hermitian matrix,
+ * A x = lambda x, with lambda in an open interval I = (emin, emax) (Sec. 1, eq. 1 with B = I).
+ * The library exposes the two steps of the FEAST iteration (Appendix, FEAST algorithm) and
+ * the whole iteration:
+ *   feast_filter_apply   step 1, Q = rho(A) X by the quadrature of Sec. 1 eq.
+ *                        (contour_int_quad);
+ *   feast_rayleigh_ritz  step 2 (A' = Q^H A Q on an orthonormalised Q, reduced
+ *                        eigenproblem, X = Q W) plus the residuals of step 3;
+ *   feast_solve          the loop 1-2-3 until max_{lambda_k in I} res_k <= tol.
+ *
+ * Conventions for every entry point
+ *   - Matrices are column-major with a leading dimension (LAPACK layout).  Complex data is
+ *     interleaved (re, im) double pairs (std::complex<double>, numpy/torch complex128).
+ *     A row-major Hermitian A read as column-major is conj(A): pass column-major storage.
+ *   - A, X, X0 and Q are DEVICE pointers owned by the caller; the library never frees them.
+ *     lambda, res, m, iters and trace are HOST pointers, written after the call has
+ *     synchronised its stream.  The library allocates its own workspace on the handle's
+ *     device (factor cache, right-hand-side blocks, reduced matrices) and frees it in
+ *     feast_destroy.
+ *   - dtype FEAST_R64: A real symmetric (double), X/Q real (double).  FEAST_C128: A complex
+ *     Hermitian, X/Q complex.  Only the lower or upper triangle is not enough: the full A is
+ *     read.
+ *   - The quadrature (readings of Sec. 1, which only says "Gauss quadrature"): circle with
+ *     centre c = (emin+emax)/2 and radius r = (emax-emin)/2, n_c Gauss-Legendre nodes on the
+ *     upper half circle theta_j = (pi/2)(1 - x_j), z_j = c + r e^{i theta_j}, weights
+ *     omega_j = (w_j/4) r e^{i theta_j}; the lower half enters through the adjoint solves
+ *     (complex A) or a real part (real A).  n_c is the number of factorizations.
+ *   - A handle is bound to the HIP device current at feast_create and to one stream; it is
+ *     not thread-safe.
+ *
+ * Return codes: 0 success; -i argument i invalid (checked on the host before any device
+ * work); FEAST_ERR_ALLOC (-100) device allocation failed; FEAST_ERR_HIP (-101) HIP runtime
+ * error (message in feast_last_error); FEAST_ERR_UNSUPPORTED (-102) option not available;
+ * positive codes are the FEAST outcomes listed below.
+ */
+#ifndef FEAST_MI355X_H
+#define FEAST_MI355X_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct feast_ctx* feast_handle;
+
+typedef enum { FEAST_R64 = 0, FEAST_C128 = 1 } feast_dtype;
+
+/* Arithmetic of the shifted factorizations and solves.  FEAST_FP64: everything in FP64.
+ * FEAST_FP32_IR: LU factors and correction solves in FP32 complex (FP32 matrix cores), with
+ * iterative refinement whose residuals X - (z_j I - A) Y and updates are FP64, to the FP64
+ * accuracy of the filtered block.  The Rayleigh-Ritz step is FP64 in both modes. */
+typedef enum { FEAST_FP64 = 0, FEAST_FP32_IR = 1 } feast_precision;
+
+typedef struct {
+  int n_c;          /* quadrature nodes on the upper half circle (>= 1) */
+  int m0;           /* subspace size, more than the number of eigenvalues in I */
+  int max_iter;     /* FEAST iterations (>= 1) */
+  int refine_max;   /* FP32_IR: refinement steps per filter application (>= 1) */
+  double tol;       /* stop when max residual over Ritz values in I <= tol (> 0) */
+  double anorm;     /* ||A||_2 used to scale residuals; <= 0: estimated by power iteration */
+  feast_precision prec;
+  unsigned long long seed; /* seeds the Gaussian start block when X0 == NULL */
+} feast_opts;
+
+#define FEAST_OK 0
+#define FEAST_NOT_CONVERGED 1 /* max_iter reached; outputs hold the last iterate */
+#define FEAST_M0_TOO_SMALL 2  /* >= m0 Ritz values inside I at iteration >= 2 */
+#define FEAST_NO_EIGENVALUES 3 /* no Ritz value inside I at two consecutive iterations */
+#define FEAST_B_NOT_SPD 4      /* the filtered block is rank deficient (Q^H Q singular) */
+#define FEAST_NONFINITE 5      /* NaN/Inf in A, X or an intermediate */
+#define FEAST_ZERO_PIVOT 6     /* exact zero pivot in a shifted factorization */
+#define FEAST_ERR_ALLOC (-100)
+#define FEAST_ERR_HIP (-101)
+#define FEAST_ERR_UNSUPPORTED (-102)
+
+/* Create a handle on the current HIP device.  hip_stream: a hipStream_t to run on, or NULL
+ * for the null stream.  Returns 0 or -1 (h NULL) / FEAST_ERR_HIP. */
+int feast_create(feast_handle* h, void* hip_stream);
+/* Release all workspace of h.  Safe on NULL. */
+int feast_destroy(feast_handle h);
+/* Static text for a return code. */
+const char* feast_status_string(int status);
+/* Text of the last HIP error seen by h (empty if none). */
+const char* feast_last_error(feast_handle h);
+/* Drop the cached factorizations (call after modifying A in place). */
+void feast_invalidate(feast_handle h);
+
+/* Step 1 of the FEAST algorithm (Appendix) with the quadrature of Sec. 1 eq.
+ * (contour_int_quad):  Q = sum_j [omega_j (z_j I - A)^{-1} + conj(omega_j) (conj(z_j) I - A)^{-1}] X
+ * (for FEAST_R64: Q = sum_j 2 Re(omega_j (z_j I - A)^{-1} X)).
+ *   A: n x n (lda >= n); X: n x m0 (ldx >= n); Q: n x m0 output (ldq >= n), must not alias X.
+ *   The n_c factorizations of z_j I - A are cached in h, keyed by (A pointer, n, lda, dtype,
+ *   emin, emax, n_c, prec); call feast_invalidate after changing A in place.
+ * Argument positions for negative codes: h=1 dt=2 n=3 A=4 lda=5 emin=6 emax=7 (needs
+ * emin < emax) n_c=8 prec=9 X=10 ldx=11 m0=12 (1 <= m0 <= n) Q=13 ldq=14.
+ * Positive returns: FEAST_ZERO_PIVOT, FEAST_NONFINITE. */
+int feast_filter_apply(feast_handle h, feast_dtype dt, int n, const void* A, int lda,
+                       double emin, double emax, int n_c, feast_precision prec, const void* X,
+                       int ldx, int m0, void* Q, int ldq);
+
+/* Step 2 of the FEAST algorithm (Appendix) and the residuals of step 3.
+ *   In: Q (n x m0, ldq), any basis of full rank.  Q is orthonormalised (Cholesky-QR, twice),
+ *   A' = Q^H A Q is diagonalised (FP64 Jacobi), and Q is overwritten by the Ritz vectors
+ *   X = Q W (unit 2-norm, ascending Ritz values).
+ *   Out (host): lambda[m0] ascending, res[m0] = ||A x_k - lambda_k x_k||_2 / anorm,
+ *   *m = number of lambda_k in the open interval (emin, emax).
+ * Argument positions: h=1 dt=2 n=3 A=4 lda=5 Q=6 ldq=7 m0=8 emin=9 emax=10 anorm=11 (> 0)
+ * lambda=12 res=13 m=14.  Positive returns: FEAST_B_NOT_SPD, FEAST_NONFINITE. */
+int feast_rayleigh_ritz(feast_handle h, feast_dtype dt, int n, const void* A, int lda, void* Q,
+                        int ldq, int m0, double emin, double emax, double anorm, double* lambda,
+                        double* res, int* m);
+
+/* The FEAST algorithm (Appendix): X_0 = X0 (n x m0, leading dimension ldx; or a seeded
+ * Gaussian block when X0 == NULL);
+ * repeat  Q = rho(A) X_i;  Rayleigh-Ritz on Q;  X_{i+1} = all m0 Ritz vectors  until the
+ * largest residual of the Ritz pairs inside I is <= opt->tol.
+ *   X: n x m0 output (ldx >= n), may equal X0 only if ldx matches.
+ *   lambda[m0], res[m0], *m, *iters: host outputs of the last iterate.
+ *   trace: NULL or host array of opt->max_iter doubles; trace[i-1] = largest in-interval
+ *   residual after iteration i.
+ * Argument positions: h=1 dt=2 n=3 A=4 lda=5 emin=6 emax=7 opt=8 (n_c, m0, max_iter, tol,
+ * prec, refine_max checked) X0=9 X=10 ldx=11 lambda=12 res=13 m=14 iters=15.
+ * Returns FEAST_OK, FEAST_NOT_CONVERGED, FEAST_M0_TOO_SMALL, FEAST_NO_EIGENVALUES,
+ * FEAST_B_NOT_SPD, FEAST_NONFINITE, FEAST_ZERO_PIVOT or an error. */
+int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, double emin,
+                double emax, const feast_opts* opt, const void* X0, void* X, int ldx,
+                double* lambda, double* res, int* m, int* iters, double* trace);
+
+/* Phase timings of the last feast_solve / feast_filter_apply / feast_rayleigh_ritz call, in
+ * milliseconds measured with HIP events on the handle's stream:
+ * out[0] factorization (shift + LU + diagonal-block inverses), out[1] triangular solves,
+ * out[2] accumulation, out[3] Rayleigh-Ritz, out[4] refinement (FP32_IR), out[5] total.
+ * Returns the number of values written (<= count). */
+int feast_get_timings(feast_handle h, double* out, int count);
+
+/* Kernel-level profiling: when enabled, every matrix-core GEMM launch is bracketed with HIP
+ * events on the handle's stream and attributed to a class.  Classes: 0 LU trailing update,
+ * 1 triangular-solve sweeps, 2 Rayleigh-Ritz, 3 refinement residual, 4 other.
+ * feast_get_kernel_stats returns total kernel milliseconds, launch count and dense GEMM
+ * flops (8 M N K per complex product) accumulated since profiling was enabled. */
+int feast_set_profiling(feast_handle h, int on);
+int feast_get_kernel_stats(feast_handle h, int kclass, double* total_ms, long long* launches,
+                           double* dense_flops);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

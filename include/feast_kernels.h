@@ -1,0 +1,42 @@
+/* feast_kernels.h -- building blocks of the MI355X FEAST hot path, exported for kernel-level
+ * parity tests and measurements.  Same conventions as feast.h: column-major, interleaved
+ * complex, device pointers owned by the caller, hip_stream may be NULL.  Every call is
+ * asynchronous on hip_stream except where it says it synchronises.  Returns 0, a negative
+ * argument position, or FEAST_ERR_HIP (-101).
+ */
+#ifndef FEAST_MI355X_KERNELS_H
+#define FEAST_MI355X_KERNELS_H
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C = alpha op(A) op(B) + beta C on the matrix cores; op: 0 = N, 1 = T, 2 = C (conjugate
+ * transpose).  prec 0: complex128 data and FP64 MFMA; prec 1: complex64 data and FP32 MFMA.
+ * alpha, beta: host arrays {re, im}.  A and B may be NULL when K == 0 (C = beta C).  This is the dense contraction used by the LU trailing
+ * updates, the block triangular sweeps and Q^H A Q (Sec. 1 linear solves; Appendix step 2).
+ * Argument positions: prec=1 opA=2 opB=3 M=4 N=5 K=6 alpha=7 A=8 lda=9 B=10 ldb=11 beta=12
+ * C=13 ldc=14. */
+int feast_kern_gemm(int prec, int opA, int opB, int M, int N, int K, const double* alpha,
+                    const void* A, long lda, const void* B, long ldb, const double* beta,
+                    void* C, long ldc, void* hip_stream);
+
+/* Batched LU with partial pivoting of M_j = z_j I - A (complex Hermitian A, n x n, lda), the
+ * factorizations behind each quadrature term of Sec. 1 eq. (contour_int_quad).
+ * z: host array of 2*nc doubles (interleaved nodes).  np = n rounded up as the library pads
+ * (returned in *np_out when LU is NULL, without other work).  LU: nc blocks of np x np
+ * (ld np, complex128 for prec 0, complex64 for prec 1) receiving unit-lower L and U; perm:
+ * nc blocks of np ints with (P M)[r] = M[perm[r]].  Synchronises the stream; returns 6 on an
+ * exact zero pivot. */
+int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, const double* z, void* LU,
+                  int* perm, int* np_out, void* hip_stream);
+
+/* Parallel-order two-sided Jacobi eigendecomposition of a Hermitian m x m matrix H
+ * (ld m, complex128, not modified): the reduced eigenproblem of the Appendix, step 2.i.
+ * d: device m doubles (eigenvalues ascending); W: device m x m eigenvectors (ld m).
+ * Synchronises the stream; returns the sweep count (>= 0) or -1 if not converged. */
+int feast_kern_jacobi(const void* H, int m, double* d, void* W, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

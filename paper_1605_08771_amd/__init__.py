@@ -1,0 +1,270 @@
+"""Python binding of libfeast_mi355x.so (the MI355X FEAST hot path, include/feast.h).
+
+Argument marshalling only: device arrays are torch tensors on a HIP device, passed to the
+C-ABI by pointer; every step of the computation runs in the library's kernels.  Matrices
+must be column-major (torch stride (1, ld)); `fortran(t)` makes such a copy.  dtype is
+chosen from the tensor: float64 -> FEAST_R64 (real symmetric), complex128 -> FEAST_C128
+(complex Hermitian).
+
+There is no CPU fallback: if the shared library is missing, `lib()` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfeast_mi355x.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "feast.h")
+
+FEAST_R64, FEAST_C128 = 0, 1
+FEAST_FP64, FEAST_FP32_IR = 0, 1
+STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "M0_TOO_SMALL", 3: "NO_EIGENVALUES",
+          4: "B_NOT_SPD", 5: "NONFINITE", 6: "ZERO_PIVOT", -100: "ERR_ALLOC",
+          -101: "ERR_HIP", -102: "ERR_UNSUPPORTED"}
+KCLASS = {"lu": 0, "solve": 1, "rr": 2, "refine": 3, "other": 4}
+
+
+class FeastOpts(ctypes.Structure):
+    _fields_ = [("n_c", ctypes.c_int), ("m0", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("refine_max", ctypes.c_int), ("tol", ctypes.c_double),
+                ("anorm", ctypes.c_double), ("prec", ctypes.c_int),
+                ("seed", ctypes.c_ulonglong)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def header_functions():
+    """Names of the functions declared in include/feast.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(feast_[a-z_0-9]+)\s*\(", txt)))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.feast_create.argtypes = [ctypes.POINTER(_vp), _vp]
+        L.feast_destroy.argtypes = [_vp]
+        L.feast_status_string.argtypes = [ctypes.c_int]
+        L.feast_status_string.restype = ctypes.c_char_p
+        L.feast_last_error.argtypes = [_vp]
+        L.feast_last_error.restype = ctypes.c_char_p
+        L.feast_invalidate.argtypes = [_vp]
+        L.feast_invalidate.restype = None
+        L.feast_filter_apply.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                         ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp,
+                                         ctypes.c_int]
+        L.feast_rayleigh_ritz.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int,
+                                          _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, _dp, _dp, _ip]
+        L.feast_solve.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int,
+                                  ctypes.c_double, ctypes.c_double, ctypes.POINTER(FeastOpts),
+                                  _vp, _vp, ctypes.c_int, _dp, _dp, _ip, _ip, _dp]
+        L.feast_get_timings.argtypes = [_vp, _dp, ctypes.c_int]
+        L.feast_set_profiling.argtypes = [_vp, ctypes.c_int]
+        L.feast_get_kernel_stats.argtypes = [_vp, ctypes.c_int, _dp,
+                                             ctypes.POINTER(ctypes.c_longlong), _dp]
+        ci, cl = ctypes.c_int, ctypes.c_long
+        L.feast_kern_gemm.argtypes = [ci, ci, ci, ci, ci, ci, _dp, _vp, cl, _vp, cl, _dp, _vp,
+                                      cl, _vp]
+        L.feast_kern_lu.argtypes = [ci, _vp, ci, ci, ci, _dp, _vp, _ip, _ip, _vp]
+        L.feast_kern_jacobi.argtypes = [_vp, ci, _vp, _vp, _vp]
+        _lib = L
+    return _lib
+
+
+def fortran(t):
+    """Column-major copy of a 2-D torch tensor (stride (1, rows))."""
+    return t.mT.contiguous().mT
+
+
+def _ld(t, name):
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    if t.numel() == 0:
+        return max(1, t.shape[0])
+    if t.stride(0) != 1 or t.stride(1) < max(1, t.shape[0]):
+        raise ValueError(f"{name} must be column-major (use fortran(t))")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the HIP device")
+    return t.stride(1)
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.complex128:
+        return FEAST_C128
+    if t.dtype == torch.float64:
+        return FEAST_R64
+    raise TypeError("A must be float64 (real symmetric) or complex128 (Hermitian)")
+
+
+class FeastError(RuntimeError):
+    def __init__(self, code, where, msg=""):
+        super().__init__(f"{where}: status {code} ({STATUS.get(code, 'invalid argument')}) {msg}")
+        self.code = code
+
+
+class Feast:
+    """One library handle bound to the current torch stream of the current device."""
+
+    def __init__(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        h = _vp()
+        st = lib().feast_create(ctypes.byref(h), _vp(stream.cuda_stream))
+        if st != 0:
+            raise FeastError(st, "feast_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().feast_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self):
+        return lib().feast_last_error(self.h).decode()
+
+    def invalidate(self):
+        lib().feast_invalidate(self.h)
+
+    # ---------------------------------------------------------------- entry points
+    def filter_apply(self, A, X, emin, emax, n_c, prec=FEAST_FP64, Q=None):
+        import torch
+        dt = _dtype_code(A)
+        lda, ldx = _ld(A, "A"), _ld(X, "X")
+        n, m0 = X.shape
+        if Q is None:
+            Q = fortran(torch.empty((n, m0), dtype=X.dtype, device=X.device))
+        ldq = _ld(Q, "Q")
+        st = lib().feast_filter_apply(self.h, dt, n, _vp(A.data_ptr()), lda, emin, emax, n_c,
+                                      prec, _vp(X.data_ptr()), ldx, m0, _vp(Q.data_ptr()), ldq)
+        return st, Q
+
+    def rayleigh_ritz(self, A, Q, emin, emax, anorm):
+        """Q is overwritten by the Ritz vectors. Returns (status, lam, res, m)."""
+        import numpy as np
+        dt = _dtype_code(A)
+        lda, ldq = _ld(A, "A"), _ld(Q, "Q")
+        n, m0 = Q.shape
+        lam = np.zeros(m0)
+        res = np.zeros(m0)
+        m = ctypes.c_int(0)
+        st = lib().feast_rayleigh_ritz(self.h, dt, n, _vp(A.data_ptr()), lda,
+                                       _vp(Q.data_ptr()), ldq, m0, emin, emax, anorm,
+                                       lam.ctypes.data_as(_dp), res.ctypes.data_as(_dp),
+                                       ctypes.byref(m))
+        return st, lam, res, m.value
+
+    def solve(self, A, emin, emax, m0, n_c=8, tol=1e-12, max_iter=50, anorm=0.0,
+              prec=FEAST_FP64, refine_max=4, X0=None, seed=0, X=None):
+        import numpy as np
+        import torch
+        dt = _dtype_code(A)
+        lda = _ld(A, "A")
+        n = A.shape[0]
+        if X is None:
+            X = fortran(torch.empty((n, m0), dtype=A.dtype, device=A.device))
+        ldx = _ld(X, "X")
+        if X0 is not None and _ld(X0, "X0") != ldx:
+            raise ValueError("X0 and X must share the leading dimension")
+        opts = FeastOpts(n_c=n_c, m0=m0, max_iter=max_iter, refine_max=refine_max, tol=tol,
+                         anorm=anorm, prec=prec, seed=seed)
+        lam = np.zeros(m0)
+        res = np.zeros(m0)
+        trace = np.zeros(max_iter)
+        m = ctypes.c_int(0)
+        iters = ctypes.c_int(0)
+        st = lib().feast_solve(self.h, dt, n, _vp(A.data_ptr()), lda, emin, emax,
+                               ctypes.byref(opts), _vp(X0.data_ptr()) if X0 is not None else None,
+                               _vp(X.data_ptr()), ldx, lam.ctypes.data_as(_dp),
+                               res.ctypes.data_as(_dp), ctypes.byref(m), ctypes.byref(iters),
+                               trace.ctypes.data_as(_dp))
+        return dict(status=st, X=X, lam=lam, res=res, m=m.value, iters=iters.value,
+                    trace=trace[: iters.value])
+
+    # ---------------------------------------------------------------- building blocks
+    def gemm(self, opA, opB, A, B, C, alpha=1.0, beta=0.0, M=None, N=None, K=None):
+        """C = alpha op(A) op(B) + beta C on the matrix cores (complex128 or complex64)."""
+        import torch
+        prec = 0 if A.dtype == torch.complex128 else 1
+        lda, ldb, ldc = _ld(A, "A"), _ld(B, "B"), _ld(C, "C")
+        M = C.shape[0] if M is None else M
+        N = C.shape[1] if N is None else N
+        if K is None:
+            K = A.shape[1] if opA == 0 else A.shape[0]
+        al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+        be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
+        st = lib().feast_kern_gemm(prec, opA, opB, M, N, K, al, _vp(A.data_ptr()), lda,
+                                   _vp(B.data_ptr()), ldb, be, _vp(C.data_ptr()), ldc,
+                                   _vp(self._stream.cuda_stream))
+        return st
+
+    def lu(self, A, z, prec=0):
+        """Factors of z_j I - A for the nodes z (numpy complex array).  Returns
+        (status, LU [nc, np, np] tensor in column-major blocks, perm [nc, np])."""
+        import numpy as np
+        import torch
+        lda = _ld(A, "A")
+        n = A.shape[0]
+        zz = np.ascontiguousarray(np.asarray(z, dtype=np.complex128)).view(np.float64)
+        nc = len(zz) // 2
+        npo = ctypes.c_int()
+        lib().feast_kern_lu(prec, _vp(A.data_ptr()), lda, n, nc, zz.ctypes.data_as(_dp), None,
+                            None, ctypes.byref(npo), None)
+        np_ = npo.value
+        dt = torch.complex128 if prec == 0 else torch.complex64
+        LU = torch.empty((nc, np_, np_), dtype=dt, device=A.device)
+        perm = torch.empty((nc, np_), dtype=torch.int32, device=A.device)
+        st = lib().feast_kern_lu(prec, _vp(A.data_ptr()), lda, n, nc, zz.ctypes.data_as(_dp),
+                                 _vp(LU.data_ptr()), ctypes.cast(ctypes.c_void_p(perm.data_ptr()), _ip),
+                                 None, _vp(self._stream.cuda_stream))
+        # blocks are column-major: element (r, c) of node j at LU[j].flatten()[r + c*np]
+        return st, LU.transpose(1, 2), perm
+
+    def jacobi(self, H):
+        import torch
+        m = H.shape[0]
+        Hf = fortran(H)
+        d = torch.empty(m, dtype=torch.float64, device=H.device)
+        W = fortran(torch.empty((m, m), dtype=H.dtype, device=H.device))
+        sweeps = lib().feast_kern_jacobi(_vp(Hf.data_ptr()), m, _vp(d.data_ptr()),
+                                         _vp(W.data_ptr()), _vp(self._stream.cuda_stream))
+        return sweeps, d, W
+
+    # ---------------------------------------------------------------- measurement
+    def timings(self):
+        out = (ctypes.c_double * 6)()
+        lib().feast_get_timings(self.h, out, 6)
+        keys = ["factor_ms", "solve_ms", "accumulate_ms", "rr_ms", "refine_ms", "total_ms"]
+        return dict(zip(keys, list(out)))
+
+    def set_profiling(self, on=True):
+        lib().feast_set_profiling(self.h, int(on))
+
+    def kernel_stats(self, kclass):
+        ms = ctypes.c_double(0)
+        n = ctypes.c_longlong(0)
+        fl = ctypes.c_double(0)
+        lib().feast_get_kernel_stats(self.h, KCLASS[kclass], ctypes.byref(ms), ctypes.byref(n),
+                                     ctypes.byref(fl))
+        return dict(ms=ms.value, launches=n.value, dense_flops=fl.value)

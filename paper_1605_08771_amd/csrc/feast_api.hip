@@ -1,0 +1,805 @@
+// C-ABI of the FEAST hot path: handle, factor cache, filter application, Rayleigh-Ritz and
+// the FEAST loop (Appendix, FEAST algorithm).  Host code only orchestrates launches on the
+// handle's stream; every arithmetic step of the path runs in this library's kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/feast.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace feast;
+
+namespace {
+
+// ---------------------------------------------------------------------------------------
+// Gauss-Legendre nodes/weights (the "Gauss quadrature" of Sec. 1) by the Golub-Welsch
+// characterisation: the nodes are the eigenvalues of the symmetric tridiagonal Jacobi matrix
+// of the Legendre recurrence (zero diagonal, off-diagonal k / sqrt(4k^2 - 1)), found here by
+// Sturm-sequence bisection; the weight of node x is 2 v_0^2 = 1 / sum_k p_k(x)^2 with p_k
+// the Legendre polynomials normalised on [-1, 1] (Christoffel function).
+// ---------------------------------------------------------------------------------------
+int sturm_count(int n, double x) {  // number of eigenvalues < x
+  int cnt = 0;
+  double q = -x;
+  if (q < 0) cnt++;
+  for (int k = 1; k < n; ++k) {
+    double b2 = (double)k * k / (4.0 * k * k - 1.0);
+    if (q == 0.0) q = 1e-300;
+    q = -x - b2 / q;
+    if (q < 0) cnt++;
+  }
+  return cnt;
+}
+
+void gauss_legendre_gw(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {  // i-th smallest eigenvalue in (-1, 1)
+    double lo = -1.0, hi = 1.0;
+    for (int it = 0; it < 200 && hi - lo > 0; ++it) {
+      double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (sturm_count(n, mid) > i) hi = mid;
+      else lo = mid;
+    }
+    double xi = 0.5 * (lo + hi);
+    // orthonormal Legendre values p_k(x) = sqrt((2k+1)/2) P_k(x)
+    double pkm1 = 1.0, pk = xi, s = 0.5;  // p_0^2 = 1/2
+    if (n > 1) s += 1.5 * xi * xi;
+    for (int k = 1; k + 1 < n; ++k) {
+      double pk1 = ((2.0 * k + 1.0) * xi * pk - k * pkm1) / (k + 1.0);
+      pkm1 = pk;
+      pk = pk1;
+      s += (2.0 * (k + 1) + 1.0) / 2.0 * pk * pk;
+    }
+    x[i] = xi;
+    w[i] = 1.0 / s;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <typename T>
+  T* get(size_t count) {
+    size_t need = count * sizeof(T);
+    if (need == 0) need = 256;
+    if (need > bytes) {
+      if (p) FEAST_HIP(hipFree(p));
+      p = nullptr;
+      bytes = 0;
+      hipError_t e = hipMalloc(&p, need);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        throw std::bad_alloc();
+      }
+      bytes = need;
+    }
+    return (T*)p;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+struct EventPool {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  hipEvent_t take() {
+    if (used == ev.size()) {
+      hipEvent_t e;
+      FEAST_HIP(hipEventCreate(&e));
+      ev.push_back(e);
+    }
+    return ev[used++];
+  }
+  void reset() { used = 0; }
+  ~EventPool() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+constexpr int NCLASS = 5;
+enum { K_LU = 0, K_SOLVE = 1, K_RR = 2, K_REFINE = 3, K_OTHER = 4 };
+
+struct KernelProfiler : GemmProfiler {
+  bool on = false;
+  int cls = K_OTHER;
+  EventPool pool;
+  struct Rec {
+    hipEvent_t a, b;
+    int cls;
+    double flops;
+  };
+  std::vector<Rec> pending;
+  hipEvent_t cur_a = nullptr;
+  double ms[NCLASS] = {0}, flops[NCLASS] = {0};
+  long long launches[NCLASS] = {0};
+  void begin(hipStream_t s) override {
+    cur_a = pool.take();
+    FEAST_HIP(hipEventRecord(cur_a, s));
+  }
+  void end(hipStream_t s, double f) override {
+    hipEvent_t b = pool.take();
+    FEAST_HIP(hipEventRecord(b, s));
+    pending.push_back({cur_a, b, cls, f});
+  }
+  void flush() {  // stream must be synchronised
+    for (auto& r : pending) {
+      float t = 0;
+      FEAST_HIP(hipEventElapsedTime(&t, r.a, r.b));
+      ms[r.cls] += t;
+      flops[r.cls] += r.flops;
+      launches[r.cls] += 1;
+    }
+    pending.clear();
+    pool.reset();
+  }
+};
+
+// Phase timer: pairs of events accumulated into phase totals at flush().
+struct PhaseTimer {
+  EventPool pool;
+  struct Rec {
+    hipEvent_t a, b;
+    int phase;
+  };
+  std::vector<Rec> pending;
+  double ms[6] = {0};
+  hipEvent_t mark(hipStream_t s) {
+    hipEvent_t e = pool.take();
+    FEAST_HIP(hipEventRecord(e, s));
+    return e;
+  }
+  void add(hipEvent_t a, hipEvent_t b, int phase) { pending.push_back({a, b, phase}); }
+  void flush() {
+    for (auto& r : pending) {
+      float t = 0;
+      FEAST_HIP(hipEventElapsedTime(&t, r.a, r.b));
+      ms[r.phase] += t;
+    }
+    pending.clear();
+    pool.reset();
+  }
+  void clear() {
+    for (double& v : ms) v = 0;
+  }
+};
+enum { P_FACTOR = 0, P_SOLVE = 1, P_ACC = 2, P_RR = 3, P_REFINE = 4, P_TOTAL = 5 };
+
+struct ScopedProf {
+  KernelProfiler* kp;
+  int saved;
+  ScopedProf(KernelProfiler& p, int cls) : kp(&p), saved(p.cls) {
+    p.cls = cls;
+    g_gemm_prof = p.on ? &p : nullptr;
+  }
+  ~ScopedProf() {
+    kp->cls = saved;
+    g_gemm_prof = nullptr;
+  }
+};
+
+}  // namespace
+
+struct feast_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string last_error;
+  // factor cache
+  bool f_valid = false;
+  const void* f_A = nullptr;
+  int f_n = 0, f_lda = 0, f_dt = -1, f_nc = 0, f_prec = -1, f_np = 0, f_nbt = 0;
+  double f_emin = 0, f_emax = 0;
+  std::vector<zd> z, omega;
+  Buf b_fac, b_invL, b_invU, b_tri_tmp, b_luw, b_z, b_omega;
+  LuWork luw;
+  // complex copy of a real A (Rayleigh-Ritz operand)
+  const void* ac_A = nullptr;
+  int ac_n = 0, ac_lda = 0;
+  bool ac_valid = false;
+  Buf b_Ac;
+  // right-hand sides / solutions
+  Buf b_B, b_Z, b_Xc, b_Qc, b_X0c;
+  // Rayleigh-Ritz
+  Buf b_Q1, b_Q2, b_AQ, b_AX, b_G, b_part, b_Rinv, b_rrtmp, b_H, b_jac, b_V, b_d, b_lam, b_res,
+      b_rank, b_W, b_flag, b_diag, b_pow;
+  PhaseTimer timer;
+  KernelProfiler prof;
+};
+
+namespace {
+
+int fail_hip(feast_ctx* h, const HipError& e) {
+  h->last_error = std::string(e.what) + ": " + hipGetErrorString(e.err);
+  return FEAST_ERR_HIP;
+}
+
+int pick_nbt(int n) {
+  if (n >= 2048) return 256;
+  if (n >= 384) return 128;
+  return 64;
+}
+
+// Factorizations of z_j I - A for all nodes (cached).
+int ensure_factors(feast_ctx* h, int dt, int n, const void* A, int lda, double emin, double emax,
+                   int nc, int prec) {
+  if (h->f_valid && h->f_A == A && h->f_n == n && h->f_lda == lda && h->f_dt == dt &&
+      h->f_nc == nc && h->f_prec == prec && h->f_emin == emin && h->f_emax == emax)
+    return 0;
+  h->f_valid = false;
+  hipStream_t s = h->stream;
+  const int nbt = pick_nbt(n);
+  const int np = (n + nbt - 1) / nbt * nbt;
+  // nodes and weights
+  std::vector<double> x, w;
+  gauss_legendre_gw(nc, x, w);
+  const double c = 0.5 * (emin + emax), r = 0.5 * (emax - emin);
+  h->z.resize(nc);
+  h->omega.resize(nc);
+  for (int j = 0; j < nc; ++j) {
+    double th = 0.5 * M_PI * (1.0 - x[j]);
+    double ct = std::cos(th), st = std::sin(th);
+    h->z[j] = zmake(c + r * ct, r * st);
+    h->omega[j] = zmake(0.25 * w[j] * r * ct, 0.25 * w[j] * r * st);
+  }
+  zd* zdev = h->b_z.get<zd>(nc);
+  zd* odev = h->b_omega.get<zd>(nc);
+  FEAST_HIP(hipMemcpyAsync(zdev, h->z.data(), sizeof(zd) * nc, hipMemcpyHostToDevice, s));
+  FEAST_HIP(hipMemcpyAsync(odev, h->omega.data(), sizeof(zd) * nc, hipMemcpyHostToDevice, s));
+
+  void* luw = h->b_luw.get<char>(lu_work_bytes(np, nc));
+  lu_work_carve(h->luw, luw, np, nc);
+  hipEvent_t e0 = h->timer.mark(s);
+  int st = 0;
+  if (prec == FEAST_FP64) {
+    zd* F = h->b_fac.get<zd>((size_t)nc * np * np);
+    shift_matrices(s, A, lda, dt == FEAST_R64, n, np, zdev, nc, F);
+    if (nonfinite_check(s, F, np, np, np, h->luw.flag)) return FEAST_NONFINITE;
+    {
+      ScopedProf sp(h->prof, K_LU);
+      lu_factor_f64(s, F, np, nc, h->luw);
+    }
+    int flag = 0;
+    FEAST_HIP(hipMemcpyAsync(&flag, h->luw.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEAST_HIP(hipStreamSynchronize(s));
+    if (flag) st = FEAST_ZERO_PIVOT;
+    zd* iL = h->b_invL.get<zd>((size_t)nc * np * nbt);
+    zd* iU = h->b_invU.get<zd>((size_t)nc * np * nbt);
+    zd* tmp = h->b_tri_tmp.get<zd>((size_t)np * nbt);
+    {
+      ScopedProf sp(h->prof, K_LU);
+      tri_inverse_blocks_f64(s, F, np, nc, nbt, iL, iU, tmp);
+    }
+  } else {
+    zf* F = h->b_fac.get<zf>((size_t)nc * np * np);
+    shift_matrices_f32(s, A, lda, dt == FEAST_R64, n, np, zdev, nc, F);
+    {
+      ScopedProf sp(h->prof, K_LU);
+      lu_factor_f32(s, F, np, nc, h->luw);
+    }
+    int flag = 0;
+    FEAST_HIP(hipMemcpyAsync(&flag, h->luw.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEAST_HIP(hipStreamSynchronize(s));
+    if (flag) st = FEAST_ZERO_PIVOT;
+    zf* iL = h->b_invL.get<zf>((size_t)nc * np * nbt);
+    zf* iU = h->b_invU.get<zf>((size_t)nc * np * nbt);
+    zf* tmp = h->b_tri_tmp.get<zf>((size_t)np * nbt);
+    {
+      ScopedProf sp(h->prof, K_LU);
+      tri_inverse_blocks_f32(s, F, np, nc, nbt, iL, iU, tmp);
+    }
+  }
+  hipEvent_t e1 = h->timer.mark(s);
+  h->timer.add(e0, e1, P_FACTOR);
+  if (st) return st;
+  h->f_valid = true;
+  h->f_A = A;
+  h->f_n = n;
+  h->f_lda = lda;
+  h->f_dt = dt;
+  h->f_nc = nc;
+  h->f_prec = prec;
+  h->f_emin = emin;
+  h->f_emax = emax;
+  h->f_np = np;
+  h->f_nbt = nbt;
+  return 0;
+}
+
+// Complex n x n copy of a real A (FEAST_R64), or A itself.
+const zd* complex_A(feast_ctx* h, int dt, int n, const void* A, int lda, long* ld_out) {
+  if (dt == FEAST_C128) {
+    *ld_out = lda;
+    return (const zd*)A;
+  }
+  if (!(h->ac_valid && h->ac_A == A && h->ac_n == n && h->ac_lda == lda)) {
+    zd* Ac = h->b_Ac.get<zd>((size_t)n * n);
+    real_to_complex(h->stream, (const double*)A, lda, Ac, n, n, n);
+    h->ac_valid = true;
+    h->ac_A = A;
+    h->ac_n = n;
+    h->ac_lda = lda;
+  }
+  *ld_out = n;
+  return (const zd*)h->b_Ac.p;
+}
+
+// Q (n x m0 complex, ldq) = rho(A) X with X n x m0 complex (ldx).  Factors must be ready.
+int filter_core(feast_ctx* h, int dt, int n, int m0, const zd* X, long ldx, zd* Q, long ldq) {
+  hipStream_t s = h->stream;
+  const int np = h->f_np, nc = h->f_nc, nbt = h->f_nbt;
+  const int sides = (dt == FEAST_C128) ? 2 : 1;
+  const size_t blk = (size_t)nc * sides * np * m0;
+  const int* perm = h->luw.perm;
+  const int* pinv = h->luw.pinv;
+  if (h->f_prec == FEAST_FP64) {
+    zd* B = h->b_B.get<zd>(blk);
+    zd* Z = h->b_Z.get<zd>(blk);
+    hipEvent_t e0 = h->timer.mark(s);
+    gather_rhs(s, X, ldx, n, np, m0, nc, sides, perm, B);
+    {
+      ScopedProf sp(h->prof, K_SOLVE);
+      solve_sweeps_f64(s, (const zd*)h->b_fac.p, (const zd*)h->b_invL.p, (const zd*)h->b_invU.p,
+                       np, nc, nbt, sides, m0, B, Z);
+    }
+    hipEvent_t e1 = h->timer.mark(s);
+    accumulate(s, B, n, np, m0, nc, sides, (const zd*)h->b_omega.p, pinv, Q, ldq);
+    hipEvent_t e2 = h->timer.mark(s);
+    h->timer.add(e0, e1, P_SOLVE);
+    h->timer.add(e1, e2, P_ACC);
+    return 0;
+  }
+  return FEAST_ERR_UNSUPPORTED;
+}
+
+// Q <- Q R^{-1} with G = Q^H Q = R^H R; Q1 (nq x m0 zero-padded rows) -> Q2.
+// Returns 0, 1 on Cholesky breakdown.
+int cholqr_pass(feast_ctx* h, int n, int m0, const zd* Q1, zd* Q2, double shift_rel) {
+  hipStream_t s = h->stream;
+  const int nsplit = std::max(1, std::min(32, n / 256));
+  const int kc = (n + nsplit - 1) / nsplit;
+  zd* part = h->b_part.get<zd>((size_t)nsplit * m0 * m0);
+  zd* G = h->b_G.get<zd>((size_t)m0 * m0);
+  int* flag = h->b_flag.get<int>(64);
+  Batch b;
+  b.n1 = nsplit;
+  b.splitk = kc;
+  b.sC1 = (long)m0 * m0;
+  zgemm(s, OP_C, OP_N, m0, m0, n, zmake(1, 0), Q1, n, Q1, n, zmake(0, 0), part, m0, b);
+  reduce_partials_hermitian(s, part, nsplit, m0, G, m0);
+  if (shift_rel > 0) {
+    // sigma = shift_rel * trace(G) (trace bounds ||G||_2)
+    double* dg = h->b_diag.get<double>(m0);
+    diag_real(s, G, m0, m0, dg);
+    std::vector<double> hd(m0);
+    FEAST_HIP(hipMemcpyAsync(hd.data(), dg, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
+    FEAST_HIP(hipStreamSynchronize(s));
+    double tr = 0;
+    for (double v : hd) tr += v;
+    add_diag(s, G, m0, m0, shift_rel * tr);
+  }
+  FEAST_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+  cholesky_upper(s, G, m0, m0, flag, nullptr);
+  int hflag = 0;
+  FEAST_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  FEAST_HIP(hipStreamSynchronize(s));
+  if (hflag) return 1;
+  zd* Rinv = h->b_Rinv.get<zd>((size_t)m0 * m0);
+  zd* tmp = h->b_rrtmp.get<zd>((size_t)m0 * 64);
+  FEAST_HIP(hipMemsetAsync(Rinv, 0, sizeof(zd) * (size_t)m0 * m0, s));
+  upper_inverse(s, G, m0, m0, Rinv, m0, tmp);
+  zgemm(s, OP_N, OP_N, n, m0, m0, zmake(1, 0), Q1, n, Rinv, m0, zmake(0, 0), Q2, n);
+  return 0;
+}
+
+// Rayleigh-Ritz on Qin (n x m0 complex, ldq); Ritz vectors written back to Qin.
+int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m0, double emin,
+            double emax, double anorm, double* lam_h, double* res_h, int* m_out) {
+  hipStream_t s = h->stream;
+  ScopedProf sp(h->prof, K_RR);
+  hipEvent_t e0 = h->timer.mark(s);
+  zd* Q1 = h->b_Q1.get<zd>((size_t)n * m0);
+  zd* Q2 = h->b_Q2.get<zd>((size_t)n * m0);
+  copy_matrix(s, Qin, ldq, Q1, n, n, m0);
+  // zero columns -> rank deficient (B' singular)
+  {
+    const int nsplit = std::max(1, std::min(32, n / 256));
+    (void)nsplit;
+  }
+  // Cholesky-QR twice; shifted Cholesky-QR3 when the first Cholesky breaks down.
+  {
+    // column norms from the first Gram matrix decide exact rank deficiency
+    const int nsplit = std::max(1, std::min(32, n / 256));
+    const int kc = (n + nsplit - 1) / nsplit;
+    zd* part = h->b_part.get<zd>((size_t)nsplit * m0 * m0);
+    zd* G = h->b_G.get<zd>((size_t)m0 * m0);
+    Batch b;
+    b.n1 = nsplit;
+    b.splitk = kc;
+    b.sC1 = (long)m0 * m0;
+    zgemm(s, OP_C, OP_N, m0, m0, n, zmake(1, 0), Q1, n, Q1, n, zmake(0, 0), part, m0, b);
+    reduce_partials_hermitian(s, part, nsplit, m0, G, m0);
+    double* dg = h->b_diag.get<double>(m0);
+    diag_real(s, G, m0, m0, dg);
+    std::vector<double> hd(m0);
+    FEAST_HIP(hipMemcpyAsync(hd.data(), dg, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
+    FEAST_HIP(hipStreamSynchronize(s));
+    double mx = 0, mn = INFINITY;
+    for (double v : hd) {
+      if (!std::isfinite(v)) return FEAST_NONFINITE;
+      mx = std::max(mx, v);
+      mn = std::min(mn, v);
+    }
+    if (!(mx > 0) || !(mn > 1e-26 * mx)) return FEAST_B_NOT_SPD;
+  }
+  if (cholqr_pass(h, n, m0, Q1, Q2, 0.0) == 0) {
+    if (cholqr_pass(h, n, m0, Q2, Q1, 0.0) != 0) return FEAST_B_NOT_SPD;
+  } else {
+    const double u = 1.1102230246251565e-16;
+    const double shift = 11.0 * ((double)m0 * n + (double)m0 * (m0 + 1)) * u;
+    if (cholqr_pass(h, n, m0, Q1, Q2, shift) != 0) return FEAST_B_NOT_SPD;
+    if (cholqr_pass(h, n, m0, Q2, Q1, 0.0) != 0) return FEAST_B_NOT_SPD;
+    if (cholqr_pass(h, n, m0, Q1, Q2, 0.0) != 0) return FEAST_B_NOT_SPD;
+    std::swap(Q1, Q2);
+  }
+  // Q1 orthonormal.  A' = Q^H (A Q).
+  zd* AQ = h->b_AQ.get<zd>((size_t)n * m0);
+  zgemm(s, OP_N, OP_N, n, m0, n, zmake(1, 0), A, lda, Q1, n, zmake(0, 0), AQ, n);
+  const int nsplit = std::max(1, std::min(32, n / 256));
+  const int kc = (n + nsplit - 1) / nsplit;
+  zd* part = h->b_part.get<zd>((size_t)nsplit * m0 * m0);
+  zd* H = h->b_H.get<zd>((size_t)m0 * m0);
+  {
+    Batch b;
+    b.n1 = nsplit;
+    b.splitk = kc;
+    b.sC1 = (long)m0 * m0;
+    zgemm(s, OP_C, OP_N, m0, m0, n, zmake(1, 0), Q1, n, AQ, n, zmake(0, 0), part, m0, b);
+    reduce_partials_hermitian(s, part, nsplit, m0, H, m0);
+  }
+  const int mp = m0 + (m0 & 1);
+  double* d = h->b_d.get<double>(mp);
+  zd* V = h->b_V.get<zd>((size_t)mp * mp);
+  zd* jw = h->b_jac.get<zd>(3 * (size_t)mp * mp);
+  int* dflag = h->b_flag.get<int>(64);
+  int sweeps = jacobi_eigh(s, H, m0, d, V, jw, dflag, 40);
+  (void)sweeps;
+  double* lam = h->b_lam.get<double>(mp);
+  zd* W = h->b_W.get<zd>((size_t)m0 * m0);
+  int* rank = h->b_rank.get<int>(mp);
+  sort_eigen(s, d, V, m0, mp, lam, W, rank);
+  zd* AX = h->b_AX.get<zd>((size_t)n * m0);
+  zgemm(s, OP_N, OP_N, n, m0, m0, zmake(1, 0), Q1, n, W, m0, zmake(0, 0), Q2, n);   // X
+  zgemm(s, OP_N, OP_N, n, m0, m0, zmake(1, 0), AQ, n, W, m0, zmake(0, 0), AX, n);   // A X
+  double* res = h->b_res.get<double>(m0);
+  residual_norms(s, AX, n, Q2, n, lam, n, m0, anorm, res);
+  copy_matrix(s, Q2, n, Qin, ldq, n, m0);
+  FEAST_HIP(hipMemcpyAsync(lam_h, lam, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
+  FEAST_HIP(hipMemcpyAsync(res_h, res, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
+  hipEvent_t e1 = h->timer.mark(s);
+  h->timer.add(e0, e1, P_RR);
+  FEAST_HIP(hipStreamSynchronize(s));
+  int cnt = 0;
+  for (int k = 0; k < m0; ++k) {
+    if (!std::isfinite(lam_h[k]) || !std::isfinite(res_h[k])) return FEAST_NONFINITE;
+    if (lam_h[k] > emin && lam_h[k] < emax) cnt++;
+  }
+  *m_out = cnt;
+  return 0;
+}
+
+void finish_timing(feast_ctx* h) {
+  h->timer.flush();
+  h->prof.flush();
+}
+
+}  // namespace
+
+// =======================================================================================
+extern "C" {
+
+int feast_create(feast_handle* out, void* hip_stream) {
+  if (!out) return -1;
+  feast_ctx* h = new feast_ctx();
+  h->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    *out = nullptr;
+    return FEAST_ERR_HIP;
+  }
+  *out = h;
+  return 0;
+}
+
+int feast_destroy(feast_handle h) {
+  if (!h) return 0;
+  (void)hipStreamSynchronize(h->stream);
+  Buf* bufs[] = {&h->b_fac, &h->b_invL, &h->b_invU, &h->b_tri_tmp, &h->b_luw, &h->b_z,
+                 &h->b_omega, &h->b_Ac, &h->b_B, &h->b_Z, &h->b_Xc, &h->b_Qc, &h->b_X0c,
+                 &h->b_Q1, &h->b_Q2, &h->b_AQ, &h->b_AX, &h->b_G, &h->b_part, &h->b_Rinv,
+                 &h->b_rrtmp, &h->b_H, &h->b_jac, &h->b_V, &h->b_d, &h->b_lam, &h->b_res,
+                 &h->b_rank, &h->b_W, &h->b_flag, &h->b_diag, &h->b_pow};
+  for (Buf* b : bufs) b->release();
+  delete h;
+  return 0;
+}
+
+const char* feast_status_string(int st) {
+  switch (st) {
+    case FEAST_OK: return "converged";
+    case FEAST_NOT_CONVERGED: return "maximum number of iterations reached";
+    case FEAST_M0_TOO_SMALL: return "m0 too small: at least m0 Ritz values inside the interval";
+    case FEAST_NO_EIGENVALUES: return "no eigenvalue inside the interval";
+    case FEAST_B_NOT_SPD: return "filtered block is rank deficient (B' not positive definite)";
+    case FEAST_NONFINITE: return "non-finite value in the input or an intermediate";
+    case FEAST_ZERO_PIVOT: return "exact zero pivot in a shifted factorization";
+    case FEAST_ERR_ALLOC: return "device allocation failed";
+    case FEAST_ERR_HIP: return "HIP runtime error";
+    case FEAST_ERR_UNSUPPORTED: return "unsupported option";
+    default: return st < 0 ? "invalid argument" : "unknown status";
+  }
+}
+
+const char* feast_last_error(feast_handle h) { return h ? h->last_error.c_str() : ""; }
+
+void feast_invalidate(feast_handle h) {
+  if (!h) return;
+  h->f_valid = false;
+  h->ac_valid = false;
+}
+
+int feast_filter_apply(feast_handle h, feast_dtype dt, int n, const void* A, int lda,
+                       double emin, double emax, int n_c, feast_precision prec, const void* X,
+                       int ldx, int m0, void* Q, int ldq) {
+  if (!h) return -1;
+  if (dt != FEAST_R64 && dt != FEAST_C128) return -2;
+  if (n < 1) return -3;
+  if (!A) return -4;
+  if (lda < n) return -5;
+  if (!std::isfinite(emin)) return -6;
+  if (!std::isfinite(emax) || !(emin < emax)) return -7;
+  if (n_c < 1 || n_c > 128) return -8;
+  if (prec != FEAST_FP64 && prec != FEAST_FP32_IR) return -9;
+  if (!X) return -10;
+  if (ldx < n) return -11;
+  if (m0 < 1 || m0 > n) return -12;
+  if (!Q || Q == X) return -13;
+  if (ldq < n) return -14;
+  try {
+    hipStream_t s = h->stream;
+    h->timer.clear();
+    hipEvent_t t0 = h->timer.mark(s);
+    int st = ensure_factors(h, dt, n, A, lda, emin, emax, n_c, prec);
+    if (st) {
+      finish_timing(h);
+      return st;
+    }
+    const zd* Xc;
+    long ldxc;
+    zd* Qc;
+    long ldqc;
+    if (dt == FEAST_R64) {
+      zd* xb = h->b_Xc.get<zd>((size_t)n * m0);
+      real_to_complex(s, (const double*)X, ldx, xb, n, n, m0);
+      Xc = xb;
+      ldxc = n;
+      Qc = h->b_Qc.get<zd>((size_t)n * m0);
+      ldqc = n;
+    } else {
+      Xc = (const zd*)X;
+      ldxc = ldx;
+      Qc = (zd*)Q;
+      ldqc = ldq;
+    }
+    st = filter_core(h, dt, n, m0, Xc, ldxc, Qc, ldqc);
+    if (st == 0 && dt == FEAST_R64) complex_to_real(s, Qc, n, (double*)Q, ldq, n, m0);
+    hipEvent_t t1 = h->timer.mark(s);
+    h->timer.add(t0, t1, P_TOTAL);
+    FEAST_HIP(hipStreamSynchronize(s));
+    finish_timing(h);
+    return st;
+  } catch (const HipError& e) {
+    return fail_hip(h, e);
+  } catch (const std::bad_alloc&) {
+    return FEAST_ERR_ALLOC;
+  }
+}
+
+int feast_rayleigh_ritz(feast_handle h, feast_dtype dt, int n, const void* A, int lda, void* Q,
+                        int ldq, int m0, double emin, double emax, double anorm, double* lambda,
+                        double* res, int* m) {
+  if (!h) return -1;
+  if (dt != FEAST_R64 && dt != FEAST_C128) return -2;
+  if (n < 1) return -3;
+  if (!A) return -4;
+  if (lda < n) return -5;
+  if (!Q) return -6;
+  if (ldq < n) return -7;
+  if (m0 < 1 || m0 > n) return -8;
+  if (!std::isfinite(emin)) return -9;
+  if (!std::isfinite(emax) || !(emin < emax)) return -10;
+  if (!(anorm > 0) || !std::isfinite(anorm)) return -11;
+  if (!lambda) return -12;
+  if (!res) return -13;
+  if (!m) return -14;
+  try {
+    hipStream_t s = h->stream;
+    h->timer.clear();
+    hipEvent_t t0 = h->timer.mark(s);
+    long ldac;
+    const zd* Ac = complex_A(h, dt, n, A, lda, &ldac);
+    zd* Qc;
+    long ldqc;
+    if (dt == FEAST_R64) {
+      Qc = h->b_Qc.get<zd>((size_t)n * m0);
+      ldqc = n;
+      real_to_complex(s, (const double*)Q, ldq, Qc, n, n, m0);
+    } else {
+      Qc = (zd*)Q;
+      ldqc = ldq;
+    }
+    int st = rr_core(h, Ac, ldac, n, Qc, ldqc, m0, emin, emax, anorm, lambda, res, m);
+    if (st == 0 && dt == FEAST_R64) complex_to_real(s, Qc, n, (double*)Q, ldq, n, m0);
+    hipEvent_t t1 = h->timer.mark(s);
+    h->timer.add(t0, t1, P_TOTAL);
+    FEAST_HIP(hipStreamSynchronize(s));
+    finish_timing(h);
+    return st;
+  } catch (const HipError& e) {
+    return fail_hip(h, e);
+  } catch (const std::bad_alloc&) {
+    return FEAST_ERR_ALLOC;
+  }
+}
+
+int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, double emin,
+                double emax, const feast_opts* opt, const void* X0, void* X, int ldx,
+                double* lambda, double* res, int* m, int* iters, double* trace) {
+  if (!h) return -1;
+  if (dt != FEAST_R64 && dt != FEAST_C128) return -2;
+  if (n < 1) return -3;
+  if (!A) return -4;
+  if (lda < n) return -5;
+  if (!std::isfinite(emin)) return -6;
+  if (!std::isfinite(emax) || !(emin < emax)) return -7;
+  if (!opt || opt->n_c < 1 || opt->n_c > 128 || opt->m0 < 1 || opt->m0 > n ||
+      opt->max_iter < 1 || !(opt->tol > 0) ||
+      (opt->prec != FEAST_FP64 && opt->prec != FEAST_FP32_IR) ||
+      (opt->prec == FEAST_FP32_IR && opt->refine_max < 1))
+    return -8;
+  if (!X) return -10;
+  if (ldx < n) return -11;
+  if (!lambda) return -12;
+  if (!res) return -13;
+  if (!m) return -14;
+  if (!iters) return -15;
+  const int m0 = opt->m0;
+  try {
+    hipStream_t s = h->stream;
+    h->timer.clear();
+    hipEvent_t t0 = h->timer.mark(s);
+    long ldac;
+    const zd* Ac = complex_A(h, dt, n, A, lda, &ldac);
+    double anorm = opt->anorm;
+    if (!(anorm > 0)) {
+      zd* pw = h->b_pow.get<zd>(2 * (size_t)n);
+      double* dn = h->b_diag.get<double>(64);
+      anorm = norm2_estimate(s, Ac, ldac, n, 30, pw, dn);
+      if (!(anorm > 0)) anorm = 1.0;
+    }
+    int st = ensure_factors(h, dt, n, A, lda, emin, emax, opt->n_c, opt->prec);
+    if (st) {
+      FEAST_HIP(hipStreamSynchronize(s));
+      finish_timing(h);
+      *iters = 0;
+      *m = 0;
+      return st;
+    }
+    // working block (complex, n x m0)
+    zd* Xw = h->b_X0c.get<zd>((size_t)n * m0);
+    zd* Qf = h->b_Qc.get<zd>((size_t)n * m0);
+    if (X0) {
+      if (dt == FEAST_R64) real_to_complex(s, (const double*)X0, ldx, Xw, n, n, m0);
+      else copy_matrix(s, (const zd*)X0, ldx, Xw, n, n, m0);
+    } else {
+      if (dt == FEAST_R64) {
+        double* tmp = (double*)h->b_Xc.get<zd>((size_t)n * m0);
+        gaussian_fill(s, tmp, n, n, m0, 1, opt->seed);
+        real_to_complex(s, tmp, n, Xw, n, n, m0);
+      } else {
+        gaussian_fill(s, Xw, n, n, m0, 0, opt->seed);
+      }
+    }
+    if (nonfinite_check(s, Xw, n, n, m0, h->b_flag.get<int>(64))) {
+      finish_timing(h);
+      *iters = 0;
+      return FEAST_NONFINITE;
+    }
+    st = FEAST_NOT_CONVERGED;
+    int it = 0, prev_m = -1, mm = 0;
+    for (it = 1; it <= opt->max_iter; ++it) {
+      int fs = filter_core(h, dt, n, m0, Xw, n, Qf, n);  // step 1
+      if (fs) {
+        st = fs;
+        break;
+      }
+      int rs = rr_core(h, Ac, ldac, n, Qf, n, m0, emin, emax, anorm, lambda, res, &mm);  // step 2
+      std::swap(Xw, Qf);  // Ritz vectors become the next block
+      finish_timing(h);
+      if (rs) {
+        st = rs;
+        break;
+      }
+      double r = 0;  // step 3
+      for (int k = 0; k < m0; ++k)
+        if (lambda[k] > emin && lambda[k] < emax) r = std::max(r, res[k]);
+      if (trace) trace[it - 1] = r;
+      if (mm == 0) {
+        if (prev_m == 0) {
+          st = FEAST_NO_EIGENVALUES;
+          break;
+        }
+      } else if (mm >= m0 && it >= 2) {
+        st = FEAST_M0_TOO_SMALL;
+        break;
+      } else if (r <= opt->tol) {
+        st = FEAST_OK;
+        break;
+      }
+      prev_m = mm;
+    }
+    if (it > opt->max_iter) it = opt->max_iter;
+    *iters = it;
+    *m = mm;
+    if (dt == FEAST_R64) complex_to_real(s, Xw, n, (double*)X, ldx, n, m0);
+    else copy_matrix(s, Xw, n, (zd*)X, ldx, n, m0);
+    hipEvent_t t1 = h->timer.mark(s);
+    h->timer.add(t0, t1, P_TOTAL);
+    FEAST_HIP(hipStreamSynchronize(s));
+    finish_timing(h);
+    return st;
+  } catch (const HipError& e) {
+    return fail_hip(h, e);
+  } catch (const std::bad_alloc&) {
+    return FEAST_ERR_ALLOC;
+  }
+}
+
+int feast_get_timings(feast_handle h, double* out, int count) {
+  if (!h || !out) return 0;
+  int k = std::min(count, 6);
+  for (int i = 0; i < k; ++i) out[i] = h->timer.ms[i];
+  return k;
+}
+
+int feast_set_profiling(feast_handle h, int on) {
+  if (!h) return -1;
+  h->prof.on = (on != 0);
+  for (int c = 0; c < NCLASS; ++c) {
+    h->prof.ms[c] = 0;
+    h->prof.flops[c] = 0;
+    h->prof.launches[c] = 0;
+  }
+  return 0;
+}
+
+int feast_get_kernel_stats(feast_handle h, int kclass, double* total_ms, long long* launches,
+                           double* dense_flops) {
+  if (!h) return -1;
+  if (kclass < 0 || kclass >= NCLASS) return -2;
+  if (total_ms) *total_ms = h->prof.ms[kclass];
+  if (launches) *launches = h->prof.launches[kclass];
+  if (dense_flops) *dense_flops = h->prof.flops[kclass];
+  return 0;
+}
+
+}  // extern "C"

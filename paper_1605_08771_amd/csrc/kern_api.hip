@@ -1,0 +1,121 @@
+// Exported building blocks (include/feast_kernels.h) for kernel-level parity tests.
+#include <vector>
+
+#include "../../include/feast_kernels.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace feast;
+
+namespace {
+int pick_np(int n) {
+  int nbt = n >= 2048 ? 256 : (n >= 384 ? 128 : 64);
+  return (n + nbt - 1) / nbt * nbt;
+}
+}  // namespace
+
+extern "C" int feast_kern_gemm(int prec, int opA, int opB, int M, int N, int K,
+                               const double* alpha, const void* A, long lda, const void* B,
+                               long ldb, const double* beta, void* C, long ldc,
+                               void* hip_stream) {
+  if (prec != 0 && prec != 1) return -1;
+  if (opA < 0 || opA > 2) return -2;
+  if (opB < 0 || opB > 2) return -3;
+  if (M < 0) return -4;
+  if (N < 0) return -5;
+  if (K < 0) return -6;
+  if (!alpha) return -7;
+  if (!A && K > 0) return -8;
+  if (lda < (opA == OP_N ? M : K) || lda < 1) return -9;
+  if (!B && K > 0) return -10;
+  if (ldb < (opB == OP_N ? K : N) || ldb < 1) return -11;
+  if (!beta) return -12;
+  if (!C) return -13;
+  if (ldc < M || ldc < 1) return -14;
+  try {
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (prec == 0)
+      zgemm(s, opA, opB, M, N, K, zmake(alpha[0], alpha[1]), (const zd*)A, lda, (const zd*)B, ldb,
+            zmake(beta[0], beta[1]), (zd*)C, ldc);
+    else
+      cgemm(s, opA, opB, M, N, K, make_float2((float)alpha[0], (float)alpha[1]), (const zf*)A,
+            lda, (const zf*)B, ldb, make_float2((float)beta[0], (float)beta[1]), (zf*)C, ldc);
+  } catch (const HipError&) {
+    return -101;
+  }
+  return 0;
+}
+
+extern "C" int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, const double* z,
+                             void* LU, int* perm, int* np_out, void* hip_stream) {
+  if (prec != 0 && prec != 1) return -1;
+  if (n < 1) return -4;
+  if (!A) return -2;
+  if (lda < n) return -3;
+  if (nc < 1) return -5;
+  if (!z) return -6;
+  const int np = pick_np(n);
+  if (np_out) *np_out = np;
+  if (!LU) return 0;
+  if (!perm) return -8;
+  try {
+    hipStream_t s = (hipStream_t)hip_stream;
+    zd* zdev = nullptr;
+    void* wbuf = nullptr;
+    FEAST_HIP(hipMalloc(&zdev, sizeof(zd) * nc));
+    FEAST_HIP(hipMemcpyAsync(zdev, z, sizeof(zd) * nc, hipMemcpyHostToDevice, s));
+    FEAST_HIP(hipMalloc(&wbuf, lu_work_bytes(np, nc)));
+    LuWork w;
+    lu_work_carve(w, wbuf, np, nc);
+    if (prec == 0) {
+      shift_matrices(s, A, lda, 0, n, np, zdev, nc, (zd*)LU);
+      lu_factor_f64(s, (zd*)LU, np, nc, w);
+    } else {
+      shift_matrices_f32(s, A, lda, 0, n, np, zdev, nc, (zf*)LU);
+      lu_factor_f32(s, (zf*)LU, np, nc, w);
+    }
+    int flag = 0;
+    FEAST_HIP(hipMemcpyAsync(perm, w.perm, sizeof(int) * (size_t)nc * np, hipMemcpyDeviceToDevice, s));
+    FEAST_HIP(hipMemcpyAsync(&flag, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEAST_HIP(hipStreamSynchronize(s));
+    FEAST_HIP(hipFree(zdev));
+    FEAST_HIP(hipFree(wbuf));
+    return flag ? 6 : 0;
+  } catch (const HipError&) {
+    return -101;
+  }
+}
+
+extern "C" int feast_kern_jacobi(const void* H, int m, double* d, void* W, void* hip_stream) {
+  if (!H) return -1;
+  if (m < 1) return -2;
+  if (!d) return -3;
+  if (!W) return -4;
+  try {
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int mp = m + (m & 1);
+    zd *Hc, *V, *work;
+    double *dd, *lam;
+    int *flag, *rank;
+    FEAST_HIP(hipMalloc(&Hc, sizeof(zd) * (size_t)m * m));
+    FEAST_HIP(hipMalloc(&V, sizeof(zd) * (size_t)mp * mp));
+    FEAST_HIP(hipMalloc(&work, sizeof(zd) * 3 * (size_t)mp * mp));
+    FEAST_HIP(hipMalloc(&dd, sizeof(double) * mp));
+    FEAST_HIP(hipMalloc(&flag, 256));
+    FEAST_HIP(hipMalloc(&rank, sizeof(int) * mp));
+    lam = d;
+    copy_matrix(s, (const zd*)H, m, Hc, m, m, m);
+    int sweeps = jacobi_eigh(s, Hc, m, dd, V, work, flag, 60);
+    sort_eigen(s, dd, V, m, mp, lam, (zd*)W, rank);
+    FEAST_HIP(hipStreamSynchronize(s));
+    FEAST_HIP(hipFree(Hc));
+    FEAST_HIP(hipFree(V));
+    FEAST_HIP(hipFree(work));
+    FEAST_HIP(hipFree(dd));
+    FEAST_HIP(hipFree(flag));
+    FEAST_HIP(hipFree(rank));
+    return sweeps;
+  } catch (const HipError&) {
+    return -101;
+  }
+}

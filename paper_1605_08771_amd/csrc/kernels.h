@@ -1,0 +1,120 @@
+// Internal launchers of the FEAST MI355X library.  All device pointers; every launch is
+// asynchronous on the given stream.
+#pragma once
+#include "common.h"
+
+namespace feast {
+
+// Two nested strided batch dimensions (element strides), n1 x n2 problems.
+// With splitk > 0 the first batch dimension instead cuts K into chunks of splitk (the
+// n1 partial products go to C + b1 * sC1; sA1/sB1 are ignored).
+struct Batch {
+  int n1 = 1, n2 = 1;
+  long sA1 = 0, sA2 = 0, sB1 = 0, sB2 = 0, sC1 = 0, sC2 = 0;
+  int splitk = 0;
+};
+
+// Optional per-thread hook that brackets every GEMM launch (kernel-level profiling).
+struct GemmProfiler {
+  virtual void begin(hipStream_t s) = 0;
+  virtual void end(hipStream_t s, double dense_flops) = 0;
+  virtual ~GemmProfiler() {}
+};
+extern thread_local GemmProfiler* g_gemm_prof;
+
+// C = alpha op(A) op(B) + beta C (column-major, complex; FP64 or FP32 matrix cores).
+void zgemm(hipStream_t s, int opA, int opB, int M, int N, int K, zd alpha, const zd* A, long lda,
+           const zd* B, long ldb, zd beta, zd* C, long ldc, const Batch& bt = Batch());
+void cgemm(hipStream_t s, int opA, int opB, int M, int N, int K, zf alpha, const zf* A, long lda,
+           const zf* B, long ldb, zf beta, zf* C, long ldc, const Batch& bt = Batch());
+
+// ---- LU (lu.hip) ---------------------------------------------------------------------
+// Shifted copies M_j = z_j I - A (j < nc) of a real (is_real) or complex n x n matrix into
+// np x np factor storage (ld = np, batch stride np*np); rows/cols n..np-1 set to identity.
+void shift_matrices(hipStream_t s, const void* A, long lda, int is_real, int n, int np,
+                    const zd* z_dev, int nc, zd* M);
+void shift_matrices_f32(hipStream_t s, const void* A, long lda, int is_real, int n, int np,
+                        const zd* z_dev, int nc, zf* M);
+
+// Workspace for the batched LU with partial pivoting.
+struct LuWork {
+  int* retired = nullptr;   // nc * np, panel stamp of rows chosen as pivots
+  double* pval = nullptr;   // 2 * nc * maxwg, pivot-search partials (value)
+  int* prow = nullptr;      // 2 * nc * maxwg, pivot-search partials (row)
+  int* pivrows = nullptr;   // nc * 64, pivot rows of the current panel
+  int* moves = nullptr;     // nc * 2 * 128, (dst, src) row moves of the current panel
+  int* perm = nullptr;      // nc * np, P as a row gather: (P X)[r] = X[perm[r]]
+  int* pinv = nullptr;      // nc * np, inverse of perm
+  int* flag = nullptr;      // 1 int: set to 1 + column of the first exact zero pivot
+};
+size_t lu_work_bytes(int np, int nc);
+void lu_work_carve(LuWork& w, void* base, int np, int nc);
+
+// In-place batched LU with partial pivoting of nc matrices (np x np, ld = np).
+void lu_factor_f64(hipStream_t s, zd* M, int np, int nc, LuWork& w);
+void lu_factor_f32(hipStream_t s, zf* M, int np, int nc, LuWork& w);
+
+// ---- triangular solves (solve.hip) -----------------------------------------------------
+// Inverses of the nbt x nbt diagonal blocks of the unit-lower L and upper U factors
+// (nb = np / nbt blocks per node, stored densely with ld = nbt, node stride np*nbt).
+void tri_inverse_blocks_f64(hipStream_t s, const zd* LU, int np, int nc, int nbt, zd* invL,
+                            zd* invU, zd* tmp);
+void tri_inverse_blocks_f32(hipStream_t s, const zf* LU, int np, int nc, int nbt, zf* invL,
+                            zf* invU, zf* tmp);
+
+// Rows of X gathered by the node permutations: B0_j[r] = X[perm_j[r]] (side 0) and
+// B1_j = X (side 1); X is n x m0 (ldx), B is np x m0 per (node, side), padded with zeros.
+void gather_rhs(hipStream_t s, const zd* X, long ldx, int n, int np, int m0, int nc, int sides,
+                const int* perm, zd* B);
+void gather_rhs_f32(hipStream_t s, const zd* X, long ldx, int n, int np, int m0, int nc,
+                    int sides, const int* perm, zf* B);
+
+// Forward then backward block sweeps for all (node, side) systems.  B (input RHS, destroyed)
+// and Y (output) are [nc][sides] blocks of np x m0.
+void solve_sweeps_f64(hipStream_t s, const zd* LU, const zd* invL, const zd* invU, int np,
+                      int nc, int nbt, int sides, int m0, zd* B, zd* Y);
+void solve_sweeps_f32(hipStream_t s, const zf* LU, const zf* invL, const zf* invU, int np,
+                      int nc, int nbt, int sides, int m0, zf* B, zf* Y);
+
+// Q = sum_j omega_j Y0_j + conj(omega_j) P_j^T Y1_j (sides == 2) or sum_j 2 Re(omega_j Y0_j)
+// (sides == 1); Q is n x m0 (ldq).
+void accumulate(hipStream_t s, const zd* Y, int n, int np, int m0, int nc, int sides,
+                const zd* omega_dev, const int* pinv, zd* Q, long ldq);
+
+// ---- Rayleigh-Ritz helpers (rr.hip) -------------------------------------------------------
+void reduce_partials_hermitian(hipStream_t s, const zd* part, int nparts, int m, zd* G, int ldg);
+// Blocked Cholesky G = R^H R (upper R, in place, ld = ldg); *flag set on breakdown.
+void cholesky_upper(hipStream_t s, zd* G, int m, int ldg, int* flag, zd* tmp);
+// Rinv = R^{-1} for upper triangular R (m x m); Rinv must be zeroed by the call.
+void upper_inverse(hipStream_t s, const zd* R, int m, int ldr, zd* Rinv, int ldi, zd* tmp);
+// Cyclic parallel-order Jacobi on the Hermitian m x m matrix H (ld = m, destroyed).
+// Returns sweeps used (host sync per sweep) or -1.  d (device, m) eigenvalues unsorted,
+// V (device, m x m) eigenvectors.
+int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* dflag,
+                int max_sweeps);
+// Stable ascending sort of d; Wout = V[:, order] (first m columns), lam = d[order].
+void sort_eigen(hipStream_t s, const double* d, const zd* V, int m, int mp, double* lam, zd* W,
+                int* rank);
+// res_k = || AX_k - lam_k X_k ||_2 / anorm.
+void residual_norms(hipStream_t s, const zd* AX, long ldax, const zd* X, long ldx,
+                    const double* lam, int n, int m0, double anorm, double* res);
+void copy_matrix(hipStream_t s, const zd* src, long lds, zd* dst, long ldd, int rows, int cols);
+void real_to_complex(hipStream_t s, const double* src, long lds, zd* dst, long ldd, int rows,
+                     int cols);
+void complex_to_real(hipStream_t s, const zd* src, long lds, double* dst, long ldd, int rows,
+                     int cols);
+void fill_zero(hipStream_t s, void* p, size_t bytes);
+// diag[k] = Re G[k, k] (k < m).
+void diag_real(hipStream_t s, const zd* G, int m, int ldg, double* diag);
+// G[k, k] += sigma (k < m).
+void add_diag(hipStream_t s, zd* G, int m, int ldg, double sigma);
+// Seeded Gaussian block (counter-based splitmix64 + Box-Muller): complex entries get
+// independent N(0,1) real and imaginary parts, real entries (is_real) N(0,1).
+void gaussian_fill(hipStream_t s, void* X, long ldx, int rows, int cols, int is_real,
+                   unsigned long long seed);
+// Power-iteration estimate of ||A||_2 (iters steps from a seeded start vector).
+double norm2_estimate(hipStream_t s, const zd* A, long lda, int n, int iters, zd* work,
+                      double* dnorm);
+int nonfinite_check(hipStream_t s, const zd* a, long ld, int rows, int cols, int* dflag);
+
+}  // namespace feast

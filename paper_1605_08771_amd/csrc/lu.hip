@@ -1,0 +1,473 @@
+// Batched complex LU with partial pivoting of the shifted matrices M_j = z_j I - A, one per
+// quadrature node (the "linear system solver" of Sec. 1, eq. contour_int_quad; the nodes are
+// independent, so all n_c factorizations advance together in every launch).
+//
+// Blocked right-looking LU, panel width 64:
+//   panel: one launch per column.  Rows are never moved inside the panel ("implicit"
+//          pivoting): each launch reduces the per-workgroup pivot candidates of the previous
+//          launch, reads the pivot row, and eliminates every other active row, then leaves
+//          the candidates of the next column.  The pivot row is read-only in that launch, so
+//          workgroups never race.
+//   swaps: the panel's pivot rows are moved to the top with the fewest row moves (at most
+//          2 x 64 rows, LAPACK swap order) over all columns, and the permutation is updated;
+//   U12:   unit-lower triangular solve with the 64x64 L11 staged in LDS;
+//   A22 -= L21 U12 on the matrix cores (batched complex GEMM).
+#include "common.h"
+#include "kernels.h"
+
+namespace feast {
+
+namespace {
+
+constexpr int NBP = 64;   // panel width
+constexpr int RPW = 256;  // rows per workgroup in the panel kernels
+
+template <typename T>
+struct V2;
+template <>
+struct V2<double> {
+  typedef double2 t;
+};
+template <>
+struct V2<float> {
+  typedef float2 t;
+};
+
+template <typename v2>
+__device__ inline v2 cmul(v2 a, v2 b) {
+  v2 r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename v2>
+__device__ inline v2 crecip(v2 a) {  // 1 / a with Smith scaling
+  v2 r;
+  if (fabs(a.x) >= fabs(a.y)) {
+    auto q = a.y / a.x, d = a.x + a.y * q;
+    r.x = 1 / d;
+    r.y = -q / d;
+  } else {
+    auto q = a.x / a.y, d = a.y + a.x * q;
+    r.x = q / d;
+    r.y = -1 / d;
+  }
+  return r;
+}
+
+template <typename T>
+__global__ void shift_kernel(const void* __restrict__ A, long lda, int is_real, int n, int np,
+                             const zd* __restrict__ z, int nc, typename V2<T>::t* __restrict__ M) {
+  typedef typename V2<T>::t v2;
+  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  long total = (long)np * np;
+  if (idx >= total) return;
+  int i = (int)(idx % np), c = (int)(idx / np);
+  double ar = 0, ai = 0;
+  bool inside = (i < n && c < n);
+  if (inside) {
+    if (is_real) {
+      ar = ((const double*)A)[i + (long)c * lda];
+    } else {
+      zd a = ((const zd*)A)[i + (long)c * lda];
+      ar = a.x;
+      ai = a.y;
+    }
+  }
+  for (int j = 0; j < nc; ++j) {
+    v2 out;
+    if (inside) {
+      double re = -ar, im = -ai;
+      if (i == c) {
+        re += z[j].x;
+        im += z[j].y;
+      }
+      out.x = (T)re;
+      out.y = (T)im;
+    } else {
+      out.x = (T)(i == c ? 1.0 : 0.0);
+      out.y = (T)0;
+    }
+    M[(long)j * total + idx] = out;
+  }
+}
+
+__device__ inline void argmax_merge(double& v, int& r, double v2_, int r2) {
+  if (v2_ > v || (v2_ == v && r2 < r)) {
+    v = v2_;
+    r = r2;
+  }
+}
+
+// Block-wide (value, row) max reduction; result valid in thread 0.
+__device__ inline void block_argmax(double& v, int& r, double* sv, int* sr) {
+  const int t = threadIdx.x;
+  sv[t] = v;
+  sr[t] = r;
+  __syncthreads();
+  for (int s = RPW / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      double ov = sv[t + s];
+      int orow = sr[t + s];
+      double cv = sv[t];
+      int cr = sr[t];
+      argmax_merge(cv, cr, ov, orow);
+      sv[t] = cv;
+      sr[t] = cr;
+    }
+    __syncthreads();
+  }
+  v = sv[0];
+  r = sr[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(RPW) void panel_search_kernel(const typename V2<T>::t* __restrict__ M,
+                                                           int np, int k, double* pval,
+                                                           int* prow, int maxwg) {
+  __shared__ double sv[RPW];
+  __shared__ int sr[RPW];
+  const int node = blockIdx.y;
+  M += (long)node * np * np;
+  int row = k + blockIdx.x * RPW + threadIdx.x;
+  double v = -1.0;
+  int r = 0x7fffffff;
+  if (row < np) {
+    auto a = M[row + (long)k * np];
+    v = (double)a.x * a.x + (double)a.y * a.y;
+    r = row;
+  }
+  block_argmax(v, r, sv, sr);
+  if (threadIdx.x == 0) {
+    pval[node * maxwg + blockIdx.x] = v;
+    prow[node * maxwg + blockIdx.x] = r;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(RPW) void panel_step_kernel(
+    typename V2<T>::t* __restrict__ M, int np, int k, int w, int jj, int nwg, int maxwg,
+    const double* __restrict__ pval_in, const int* __restrict__ prow_in, double* pval_out,
+    int* prow_out, int* retired, int* pivrows, int* flag) {
+  typedef typename V2<T>::t v2;
+  __shared__ double sv[RPW];
+  __shared__ int sr[RPW];
+  __shared__ v2 upiv[NBP];
+  __shared__ int s_p;
+  __shared__ v2 s_rinv;
+  __shared__ int s_zero;
+  const int node = blockIdx.y;
+  const int t = threadIdx.x;
+  M += (long)node * np * np;
+  retired += node * np;
+  const int c = k + jj;
+  const int stamp = k + 1;
+
+  // pivot of column c from the candidates left by the previous launch
+  {
+    double v = -1.0;
+    int r = 0x7fffffff;
+    for (int q = t; q < nwg; q += RPW)
+      argmax_merge(v, r, pval_in[node * maxwg + q], prow_in[node * maxwg + q]);
+    block_argmax(v, r, sv, sr);
+    if (t == 0) {
+      bool bad = !(v > 0.0) || r < k || r >= np;  // zero column or non-finite candidates
+      s_p = bad ? c : r;
+      s_zero = bad;
+    }
+    __syncthreads();
+  }
+  const int p = s_p;
+  const int width = w - jj;  // columns c .. k+w-1
+  if (t < width) upiv[t] = M[p + (long)(c + t) * np];
+  __syncthreads();
+  if (t == 0) {
+    s_rinv = s_zero ? v2{0, 0} : crecip(upiv[0]);
+    if (s_zero && flag) atomicCAS(flag, 0, c + 1);
+  }
+  __syncthreads();
+  const v2 rinv = s_rinv;
+
+  int row = k + blockIdx.x * RPW + t;
+  double cand = -1.0;
+  int crow = 0x7fffffff;
+  if (row < np) {
+    if (row == p) {
+      retired[row] = stamp;
+      pivrows[node * NBP + jj] = p;
+    } else if (retired[row] != stamp) {
+      v2 a = M[row + (long)c * np];
+      v2 l = cmul(a, rinv);
+      M[row + (long)c * np] = l;
+      for (int q = 1; q < width; ++q) {
+        v2 m = M[row + (long)(c + q) * np];
+        v2 u = upiv[q];
+        m.x -= l.x * u.x - l.y * u.y;
+        m.y -= l.x * u.y + l.y * u.x;
+        M[row + (long)(c + q) * np] = m;
+        if (q == 1) {
+          cand = (double)m.x * m.x + (double)m.y * m.y;
+          crow = row;
+        }
+      }
+    }
+  }
+  if (jj + 1 < w) {
+    block_argmax(cand, crow, sv, sr);
+    if (t == 0) {
+      pval_out[node * maxwg + blockIdx.x] = cand;
+      prow_out[node * maxwg + blockIdx.x] = crow;
+    }
+  }
+}
+
+// One thread per node: LAPACK-order swap sequence of the panel -> list of row moves
+// (dst <- src) over the affected positions, and the same moves applied to perm.
+__global__ void panel_moves_kernel(int np, int k, int w, const int* pivrows, int* moves,
+                                   int* perm) {
+  if (threadIdx.x != 0) return;
+  const int node = blockIdx.x;
+  const int* pr = pivrows + node * NBP;
+  int pos[2 * NBP], orig[2 * NBP];
+  int cnt = 0;
+  for (int jj = 0; jj < w; ++jj) {
+    pos[cnt] = k + jj;
+    orig[cnt] = k + jj;
+    cnt++;
+  }
+  for (int jj = 0; jj < w; ++jj) {
+    int p = pr[jj];
+    if (p >= k + w) {
+      pos[cnt] = p;
+      orig[cnt] = p;
+      cnt++;
+    }
+  }
+  for (int jj = 0; jj < w; ++jj) {
+    int want = pr[jj];
+    int qa = -1, ta = -1;
+    for (int a = 0; a < cnt; ++a) {
+      if (orig[a] == want) qa = a;
+      if (pos[a] == k + jj) ta = a;
+    }
+    if (qa < 0 || ta < 0) continue;  // only after a reported zero pivot
+    int tmp = orig[ta];
+    orig[ta] = orig[qa];
+    orig[qa] = tmp;
+  }
+  int* mv = moves + node * (4 * NBP + 1);
+  int nm = 0;
+  int* pm = perm + (long)node * np;
+  int srcp[2 * NBP];
+  for (int a = 0; a < cnt; ++a) srcp[a] = pm[orig[a]];
+  for (int a = 0; a < cnt; ++a) {
+    if (pos[a] != orig[a]) {
+      mv[1 + 2 * nm] = pos[a];
+      mv[2 + 2 * nm] = orig[a];
+      nm++;
+    }
+    pm[pos[a]] = srcp[a];
+  }
+  mv[0] = nm;
+}
+
+constexpr int SWAP_COLS = 32;
+template <typename T>
+__global__ __launch_bounds__(256) void laswp_kernel(typename V2<T>::t* __restrict__ M, int np,
+                                                   const int* moves) {
+  typedef typename V2<T>::t v2;
+  const int node = blockIdx.y;
+  M += (long)node * np * np;
+  const int* mv = moves + node * (4 * NBP + 1);
+  const int nm = mv[0];
+  const int a = threadIdx.x & 127, half = threadIdx.x >> 7;
+  const int c0 = blockIdx.x * SWAP_COLS;
+  v2 vals[SWAP_COLS / 2];
+  int dst = 0, src = 0;
+  if (a < nm) {
+    dst = mv[1 + 2 * a];
+    src = mv[2 + 2 * a];
+#pragma unroll
+    for (int q = 0; q < SWAP_COLS / 2; ++q) {
+      int c = c0 + half + 2 * q;
+      if (c < np) vals[q] = M[src + (long)c * np];
+    }
+  }
+  __syncthreads();
+  if (a < nm) {
+#pragma unroll
+    for (int q = 0; q < SWAP_COLS / 2; ++q) {
+      int c = c0 + half + 2 * q;
+      if (c < np) M[dst + (long)c * np] = vals[q];
+    }
+  }
+}
+
+// U12 = L11^{-1} A12 for 64 columns per workgroup (L11 unit lower, staged in LDS).
+template <typename T>
+__global__ __launch_bounds__(256) void trsm_u12_kernel(typename V2<T>::t* __restrict__ M, int np,
+                                                       int k, int w) {
+  typedef typename V2<T>::t v2;
+  __shared__ v2 L[NBP][NBP + 1];
+  __shared__ v2 X[NBP][NBP + 1];
+  const int node = blockIdx.y;
+  M += (long)node * np * np;
+  const int t = threadIdx.x;
+  const int col0 = k + w + blockIdx.x * 64;
+  for (int e = t; e < w * w; e += 256) {
+    int r = e % w, cc = e / w;
+    L[r][cc] = M[k + r + (long)(k + cc) * np];
+  }
+  for (int e = t; e < w * 64; e += 256) {
+    int r = e % w, cc = e / w;
+    int gc = col0 + cc;
+    X[r][cc] = (gc < np) ? M[k + r + (long)gc * np] : v2{0, 0};
+  }
+  __syncthreads();
+  for (int r = 0; r < w - 1; ++r) {
+    int rows = w - 1 - r;
+    for (int e = t; e < rows * 64; e += 256) {
+      int i = r + 1 + e % rows, cc = e / rows;
+      v2 l = L[i][r], x = X[r][cc];
+      X[i][cc].x -= l.x * x.x - l.y * x.y;
+      X[i][cc].y -= l.x * x.y + l.y * x.x;
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < w * 64; e += 256) {
+    int r = e % w, cc = e / w;
+    int gc = col0 + cc;
+    if (gc < np) M[k + r + (long)gc * np] = X[r][cc];
+  }
+}
+
+__global__ void perm_init_kernel(int* perm, int np, int nc) {
+  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx < (long)np * nc) perm[idx] = (int)(idx % np);
+}
+__global__ void perm_invert_kernel(const int* perm, int* pinv, int np, int nc) {
+  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx < (long)np * nc) {
+    long node = idx / np;
+    pinv[node * np + perm[idx]] = (int)(idx % np);
+  }
+}
+
+template <typename T>
+void gemm_update(hipStream_t s, typename V2<T>::t* M, int np, int nc, int k, int w);
+template <>
+void gemm_update<double>(hipStream_t s, zd* M, int np, int nc, int k, int w) {
+  int rest = np - k - w;
+  Batch b;
+  b.n1 = nc;
+  b.sA1 = b.sB1 = b.sC1 = (long)np * np;
+  zgemm(s, OP_N, OP_N, rest, rest, w, zmake(-1, 0), M + (k + w) + (long)k * np, np,
+        M + k + (long)(k + w) * np, np, zmake(1, 0), M + (k + w) + (long)(k + w) * np, np, b);
+}
+template <>
+void gemm_update<float>(hipStream_t s, zf* M, int np, int nc, int k, int w) {
+  int rest = np - k - w;
+  Batch b;
+  b.n1 = nc;
+  b.sA1 = b.sB1 = b.sC1 = (long)np * np;
+  cgemm(s, OP_N, OP_N, rest, rest, w, make_float2(-1, 0), M + (k + w) + (long)k * np, np,
+        M + k + (long)(k + w) * np, np, make_float2(1, 0), M + (k + w) + (long)(k + w) * np, np,
+        b);
+}
+
+template <typename T>
+void lu_factor(hipStream_t s, typename V2<T>::t* M, int np, int nc, LuWork& w) {
+  const int maxwg = (np + RPW - 1) / RPW;
+  FEAST_HIP(hipMemsetAsync(w.retired, 0, sizeof(int) * (size_t)nc * np, s));
+  FEAST_HIP(hipMemsetAsync(w.flag, 0, sizeof(int), s));
+  {
+    long tot = (long)np * nc;
+    hipLaunchKernelGGL(perm_init_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, w.perm, np, nc);
+    FEAST_LAUNCH_CHECK();
+  }
+  for (int k = 0; k < np; k += NBP) {
+    const int width = (np - k < NBP) ? np - k : NBP;
+    const int nwg = (np - k + RPW - 1) / RPW;
+    double* pv[2] = {w.pval, w.pval + nc * maxwg};
+    int* pr[2] = {w.prow, w.prow + nc * maxwg};
+    hipLaunchKernelGGL((panel_search_kernel<T>), dim3(nwg, nc), dim3(RPW), 0, s, M, np, k, pv[0],
+                       pr[0], maxwg);
+    FEAST_LAUNCH_CHECK();
+    for (int jj = 0; jj < width; ++jj) {
+      hipLaunchKernelGGL((panel_step_kernel<T>), dim3(nwg, nc), dim3(RPW), 0, s, M, np, k, width,
+                         jj, nwg, maxwg, pv[jj & 1], pr[jj & 1], pv[(jj + 1) & 1],
+                         pr[(jj + 1) & 1], w.retired, w.pivrows, w.flag);
+      FEAST_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(panel_moves_kernel, dim3(nc), dim3(64), 0, s, np, k, width, w.pivrows,
+                       w.moves, w.perm);
+    FEAST_LAUNCH_CHECK();
+    hipLaunchKernelGGL((laswp_kernel<T>), dim3((np + SWAP_COLS - 1) / SWAP_COLS, nc), dim3(256),
+                       0, s, M, np, w.moves);
+    FEAST_LAUNCH_CHECK();
+    const int rest = np - k - width;
+    if (rest > 0) {
+      hipLaunchKernelGGL((trsm_u12_kernel<T>), dim3((rest + 63) / 64, nc), dim3(256), 0, s, M, np,
+                         k, width);
+      FEAST_LAUNCH_CHECK();
+      gemm_update<T>(s, M, np, nc, k, width);
+    }
+  }
+  long tot = (long)np * nc;
+  hipLaunchKernelGGL(perm_invert_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, w.perm, w.pinv,
+                     np, nc);
+  FEAST_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+size_t lu_work_bytes(int np, int nc) {
+  const int maxwg = (np + RPW - 1) / RPW;
+  size_t b = 0;
+  b += sizeof(int) * (size_t)nc * np;           // retired
+  b += sizeof(double) * 2 * (size_t)nc * maxwg;  // pval
+  b += sizeof(int) * 2 * (size_t)nc * maxwg;     // prow
+  b += sizeof(int) * (size_t)nc * NBP;           // pivrows
+  b += sizeof(int) * (size_t)nc * (4 * NBP + 1); // moves
+  b += 2 * sizeof(int) * (size_t)nc * np;        // perm, pinv
+  b += 256;                                      // flag
+  return b + 8 * 256;                            // alignment slack
+}
+
+void lu_work_carve(LuWork& w, void* base, int np, int nc) {
+  const int maxwg = (np + RPW - 1) / RPW;
+  char* p = (char*)base;
+  auto take = [&](size_t bytes) {
+    char* r = p;
+    p += (bytes + 255) & ~(size_t)255;
+    return (void*)r;
+  };
+  w.pval = (double*)take(sizeof(double) * 2 * (size_t)nc * maxwg);
+  w.retired = (int*)take(sizeof(int) * (size_t)nc * np);
+  w.prow = (int*)take(sizeof(int) * 2 * (size_t)nc * maxwg);
+  w.pivrows = (int*)take(sizeof(int) * (size_t)nc * NBP);
+  w.moves = (int*)take(sizeof(int) * (size_t)nc * (4 * NBP + 1));
+  w.perm = (int*)take(sizeof(int) * (size_t)nc * np);
+  w.pinv = (int*)take(sizeof(int) * (size_t)nc * np);
+  w.flag = (int*)take(256);
+}
+
+void shift_matrices(hipStream_t s, const void* A, long lda, int is_real, int n, int np,
+                    const zd* z_dev, int nc, zd* M) {
+  long tot = (long)np * np;
+  hipLaunchKernelGGL((shift_kernel<double>), dim3((tot + 255) / 256), dim3(256), 0, s, A, lda,
+                     is_real, n, np, z_dev, nc, M);
+  FEAST_LAUNCH_CHECK();
+}
+void shift_matrices_f32(hipStream_t s, const void* A, long lda, int is_real, int n, int np,
+                        const zd* z_dev, int nc, zf* M) {
+  long tot = (long)np * np;
+  hipLaunchKernelGGL((shift_kernel<float>), dim3((tot + 255) / 256), dim3(256), 0, s, A, lda,
+                     is_real, n, np, z_dev, nc, M);
+  FEAST_LAUNCH_CHECK();
+}
+
+void lu_factor_f64(hipStream_t s, zd* M, int np, int nc, LuWork& w) { lu_factor<double>(s, M, np, nc, w); }
+void lu_factor_f32(hipStream_t s, zf* M, int np, int nc, LuWork& w) { lu_factor<float>(s, M, np, nc, w); }
+
+}  // namespace feast

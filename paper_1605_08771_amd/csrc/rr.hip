@@ -1,0 +1,547 @@
+// Rayleigh-Ritz building blocks (Appendix, FEAST step 2; residuals of step 3):
+//   Cholesky-QR orthonormalisation of the filtered block (G = Q^H Q = R^H R, Q <- Q R^{-1}),
+//   parallel-order two-sided Jacobi for the m0 x m0 reduced matrix, eigenpair sort, and the
+//   residual norms ||A x_k - lambda_k x_k||.
+#include "common.h"
+#include "kernels.h"
+
+namespace feast {
+
+namespace {
+
+__global__ void reduce_herm_kernel(const zd* __restrict__ part, int nparts, int m,
+                                   zd* __restrict__ G, int ldg) {
+  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)m * m) return;
+  int i = (int)(idx % m), j = (int)(idx / m);
+  if (i > j) return;
+  const long mm = (long)m * m;
+  double ar = 0, ai = 0, br = 0, bi = 0;
+  for (int p = 0; p < nparts; ++p) {
+    zd a = part[p * mm + i + (long)j * m];
+    zd b = part[p * mm + j + (long)i * m];
+    ar += a.x;
+    ai += a.y;
+    br += b.x;
+    bi += b.y;
+  }
+  // (S + S^H)/2 at (i, j) and its conjugate at (j, i)
+  double re = 0.5 * (ar + br), im = 0.5 * (ai - bi);
+  if (i == j) im = 0.0;
+  G[i + (long)j * ldg] = zmake(re, im);
+  G[j + (long)i * ldg] = zmake(re, -im);
+}
+
+constexpr int CB = 64;
+
+// Unblocked upper Cholesky of the b x b diagonal block at G (ld) in LDS.
+__global__ __launch_bounds__(256) void chol_diag_kernel(zd* G, int ld, int b, int* flag) {
+  __shared__ zd S[CB][CB + 1];
+  const int t = threadIdx.x;
+  for (int e = t; e < b * b; e += 256) {
+    int r = e % b, c = e / b;
+    S[r][c] = G[r + (long)c * ld];
+  }
+  __syncthreads();
+  for (int j = 0; j < b; ++j) {
+    double d = S[j][j].x;
+    bool bad = !(d > 0.0);
+    double rjj = bad ? 1.0 : sqrt(d);
+    __syncthreads();
+    if (t == 0) {
+      if (bad && flag) atomicOr(flag, 1);
+      S[j][j] = zmake(rjj, 0.0);
+    }
+    for (int c = j + 1 + t; c < b; c += 256) S[j][c] = zscale(S[j][c], 1.0 / rjj);
+    __syncthreads();
+    // trailing: S[i][c] -= conj(S[j][i]) S[j][c] for j < i <= c
+    int rest = b - j - 1;
+    for (int e = t; e < rest * rest; e += 256) {
+      int i = j + 1 + e % rest, c = j + 1 + e / rest;
+      if (i <= c) {
+        zd u = S[j][i], v = S[j][c];
+        S[i][c] = zsub(S[i][c], zmake(u.x * v.x + u.y * v.y, u.x * v.y - u.y * v.x));
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < b * b; e += 256) {
+    int r = e % b, c = e / b;
+    G[r + (long)c * ld] = (r <= c) ? S[r][c] : zmake(0, 0);
+  }
+}
+
+// X = R11^{-H} X for a 64-column chunk: R11 (b x b upper) at R, X (b x ncols) at X.
+__global__ __launch_bounds__(256) void chol_rowpanel_kernel(const zd* R, int ld, int b, zd* X,
+                                                            int ncols) {
+  __shared__ zd Rs[CB][CB + 1];
+  __shared__ zd Xs[CB][CB + 1];
+  const int t = threadIdx.x;
+  const int c0 = blockIdx.x * 64;
+  for (int e = t; e < b * b; e += 256) {
+    int r = e % b, c = e / b;
+    Rs[r][c] = R[r + (long)c * ld];
+  }
+  for (int e = t; e < b * 64; e += 256) {
+    int r = e % b, c = e / b;
+    Xs[r][c] = (c0 + c < ncols) ? X[r + (long)(c0 + c) * ld] : zmake(0, 0);
+  }
+  __syncthreads();
+  // solve R11^H Y = X: forward, row r: y_r = (x_r - sum_{i<r} conj(R[i][r]) y_i) / R[r][r]
+  for (int r = 0; r < b; ++r) {
+    if (t < 64) Xs[r][t] = zscale(Xs[r][t], 1.0 / Rs[r][r].x);
+    __syncthreads();
+    int rows = b - r - 1;
+    for (int e = t; e < rows * 64; e += 256) {
+      int i = r + 1 + e % rows, c = e / rows;
+      zd u = Rs[r][i], y = Xs[r][c];  // conj(u) * y
+      Xs[i][c] = zsub(Xs[i][c], zmake(u.x * y.x + u.y * y.y, u.x * y.y - u.y * y.x));
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < b * 64; e += 256) {
+    int r = e % b, c = e / b;
+    if (c0 + c < ncols) X[r + (long)(c0 + c) * ld] = Xs[r][c];
+  }
+}
+
+// Inverse of the b x b (b <= 64) upper block at R into out (identity-padded in LDS).
+__global__ __launch_bounds__(256) void upper_inv_small_kernel(const zd* R, int ldr, int b, zd* out,
+                                                              int ldo) {
+  __shared__ zd Tm[CB][CB + 1];
+  __shared__ zd X[CB][CB + 1];
+  const int t = threadIdx.x;
+  for (int e = t; e < CB * CB; e += 256) {
+    int r = e % CB, c = e / CB;
+    Tm[r][c] = (r < b && c < b) ? R[r + (long)c * ldr] : zmake(r == c ? 1 : 0, 0);
+    X[r][c] = zmake(r == c ? 1 : 0, 0);
+  }
+  __syncthreads();
+  for (int r = CB - 1; r >= 0; --r) {
+    if (t < CB - r) {
+      int c = r + t;
+      X[r][c] = zdiv(X[r][c], Tm[r][r]);
+    }
+    __syncthreads();
+    int cols = CB - r;
+    for (int e = t; e < r * cols; e += 256) {
+      int i = e % r, c = r + e / r;
+      X[i][c] = zsub(X[i][c], zmul(Tm[i][r], X[r][c]));
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < b * b; e += 256) {
+    int r = e % b, c = e / b;
+    out[r + (long)c * ldo] = X[r][c];
+  }
+}
+
+// ---- Jacobi ---------------------------------------------------------------------------
+struct Rot {
+  bool active;
+  double c, s, t, a;
+  zd e;  // e^{-i phi}, phi = arg(h_pq)
+};
+
+__device__ inline Rot make_rot(const zd* __restrict__ H, int mp, int p, int q) {
+  Rot r;
+  zd hpq = H[p + (long)q * mp];
+  double hpp = H[p + (long)p * mp].x, hqq = H[q + (long)q * mp].x;
+  double a = sqrt(hpq.x * hpq.x + hpq.y * hpq.y);
+  r.a = a;
+  r.active = !(a == 0.0 || a <= 1e-17 * sqrt(fabs(hpp * hqq)));
+  if (!r.active) {
+    r.c = 1;
+    r.s = 0;
+    r.t = 0;
+    r.e = zmake(1, 0);
+    return r;
+  }
+  r.e = zmake(hpq.x / a, -hpq.y / a);
+  double tau = (hqq - hpp) / (2.0 * a);
+  double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  r.t = tt;
+  r.c = 1.0 / sqrt(1.0 + tt * tt);
+  r.s = tt * r.c;
+  return r;
+}
+
+// Pair a of round t in the round-robin ("circle") ordering of mp indices.
+__device__ inline void pair_of(int a, int t, int mp, int& p, int& q) {
+  auto f = [&](int i) { return i == 0 ? 0 : ((i - 1 + t) % (mp - 1)) + 1; };
+  int x = f(a), y = f(mp - 1 - a);
+  p = x < y ? x : y;
+  q = x < y ? y : x;
+}
+
+__global__ __launch_bounds__(256) void jacobi_round_kernel(const zd* __restrict__ Hin,
+                                                           zd* __restrict__ Hout,
+                                                           const zd* __restrict__ Vin,
+                                                           zd* __restrict__ Vout, int mp,
+                                                           int round) {
+  const int half = mp / 2;
+  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  long nA = (long)half * half;
+  if (idx < nA) {
+    int a = (int)(idx % half), b = (int)(idx / half);
+    int pa, qa, pb, qb;
+    pair_of(a, round, mp, pa, qa);
+    pair_of(b, round, mp, pb, qb);
+    Rot ra = make_rot(Hin, mp, pa, qa);
+    Rot rb = (a == b) ? ra : make_rot(Hin, mp, pb, qb);
+    zd b00 = Hin[pa + (long)pb * mp], b01 = Hin[pa + (long)qb * mp];
+    zd b10 = Hin[qa + (long)pb * mp], b11 = Hin[qa + (long)qb * mp];
+    // G = [[c, s], [-s e, c e]];  Y = G_a^H B
+    zd ga11 = zmake(ra.c, 0), ga12 = zmake(ra.s, 0);
+    zd ga21 = zscale(ra.e, -ra.s), ga22 = zscale(ra.e, ra.c);
+    zd y00 = zadd(zmul(zconj(ga11), b00), zmul(zconj(ga21), b10));
+    zd y01 = zadd(zmul(zconj(ga11), b01), zmul(zconj(ga21), b11));
+    zd y10 = zadd(zmul(zconj(ga12), b00), zmul(zconj(ga22), b10));
+    zd y11 = zadd(zmul(zconj(ga12), b01), zmul(zconj(ga22), b11));
+    zd gb11 = zmake(rb.c, 0), gb12 = zmake(rb.s, 0);
+    zd gb21 = zscale(rb.e, -rb.s), gb22 = zscale(rb.e, rb.c);
+    zd x00 = zadd(zmul(y00, gb11), zmul(y01, gb21));
+    zd x01 = zadd(zmul(y00, gb12), zmul(y01, gb22));
+    zd x10 = zadd(zmul(y10, gb11), zmul(y11, gb21));
+    zd x11 = zadd(zmul(y10, gb12), zmul(y11, gb22));
+    if (a == b && ra.active) {
+      x00 = zmake(Hin[pa + (long)pa * mp].x - ra.t * ra.a, 0);
+      x11 = zmake(Hin[qa + (long)qa * mp].x + ra.t * ra.a, 0);
+      x01 = zmake(0, 0);
+      x10 = zmake(0, 0);
+    }
+    Hout[pa + (long)pb * mp] = x00;
+    Hout[pa + (long)qb * mp] = x01;
+    Hout[qa + (long)pb * mp] = x10;
+    Hout[qa + (long)qb * mp] = x11;
+    return;
+  }
+  idx -= nA;
+  if (idx < (long)mp * half) {
+    int i = (int)(idx % mp), b = (int)(idx / mp);
+    int pb, qb;
+    pair_of(b, round, mp, pb, qb);
+    Rot rb = make_rot(Hin, mp, pb, qb);
+    zd gb11 = zmake(rb.c, 0), gb12 = zmake(rb.s, 0);
+    zd gb21 = zscale(rb.e, -rb.s), gb22 = zscale(rb.e, rb.c);
+    zd v0 = Vin[i + (long)pb * mp], v1 = Vin[i + (long)qb * mp];
+    Vout[i + (long)pb * mp] = zadd(zmul(v0, gb11), zmul(v1, gb21));
+    Vout[i + (long)qb * mp] = zadd(zmul(v0, gb12), zmul(v1, gb22));
+  }
+}
+
+__global__ void jacobi_check_kernel(const zd* __restrict__ H, int mp, int* flag) {
+  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)mp * mp) return;
+  int p = (int)(idx % mp), q = (int)(idx / mp);
+  if (p >= q) return;
+  zd hpq = H[p + (long)q * mp];
+  double a = sqrt(hpq.x * hpq.x + hpq.y * hpq.y);
+  double hpp = H[p + (long)p * mp].x, hqq = H[q + (long)q * mp].x;
+  if (!(a == 0.0 || a <= 1e-17 * sqrt(fabs(hpp * hqq)))) atomicOr(flag, 1);
+}
+
+__global__ void jacobi_init_kernel(const zd* __restrict__ H, int m, int mp, zd* __restrict__ A,
+                                   zd* __restrict__ V) {
+  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)mp * mp) return;
+  int i = (int)(idx % mp), j = (int)(idx / mp);
+  zd v;
+  if (i < m && j < m) v = H[i + (long)j * m];
+  else v = zmake(i == j ? 1e100 : 0.0, 0.0);  // padded index: decoupled, sorts last
+  A[idx] = v;
+  V[idx] = zmake(i == j ? 1.0 : 0.0, 0.0);
+}
+
+__global__ void diag_kernel(const zd* H, int mp, double* d) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < mp) d[i] = H[i + (long)i * mp].x;
+}
+
+__global__ void rank_kernel(const double* d, int mp, int* rank) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= mp) return;
+  double di = d[i];
+  int r = 0;
+  for (int j = 0; j < mp; ++j) {
+    double dj = d[j];
+    if (dj < di || (dj == di && j < i)) r++;
+  }
+  rank[i] = r;
+}
+
+__global__ void sort_copy_kernel(const double* d, const zd* V, const int* rank, int m, int mp,
+                                 double* lam, zd* W) {
+  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)m * mp) return;
+  int i = (int)(idx % m), src = (int)(idx / m);
+  int r = rank[src];
+  if (r >= m) return;
+  W[i + (long)r * m] = V[i + (long)src * mp];
+  if (i == 0) lam[r] = d[src];
+}
+
+__global__ __launch_bounds__(256) void residual_kernel(const zd* __restrict__ AX, long ldax,
+                                                       const zd* __restrict__ X, long ldx,
+                                                       const double* __restrict__ lam, int n,
+                                                       double anorm, double* res) {
+  __shared__ double sh[256];
+  const int k = blockIdx.x;
+  const double l = lam[k];
+  double s = 0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    zd a = AX[i + (long)k * ldax], x = X[i + (long)k * ldx];
+    double rr = a.x - l * x.x, ri = a.y - l * x.y;
+    s += rr * rr + ri * ri;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) res[k] = sqrt(sh[0]) / anorm;
+}
+
+__global__ void copy_kernel(const zd* src, long lds, zd* dst, long ldd, int rows, int cols) {
+  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)rows * cols) return;
+  int i = (int)(idx % rows), j = (int)(idx / rows);
+  dst[i + (long)j * ldd] = src[i + (long)j * lds];
+}
+__global__ void r2c_kernel(const double* src, long lds, zd* dst, long ldd, int rows, int cols) {
+  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)rows * cols) return;
+  int i = (int)(idx % rows), j = (int)(idx / rows);
+  dst[i + (long)j * ldd] = zmake(src[i + (long)j * lds], 0.0);
+}
+__global__ void c2r_kernel(const zd* src, long lds, double* dst, long ldd, int rows, int cols) {
+  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)rows * cols) return;
+  int i = (int)(idx % rows), j = (int)(idx / rows);
+  dst[i + (long)j * ldd] = src[i + (long)j * lds].x;
+}
+__global__ void nonfinite_kernel(const zd* a, long ld, int rows, int cols, int* flag) {
+  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)rows * cols) return;
+  int i = (int)(idx % rows), j = (int)(idx / rows);
+  zd v = a[i + (long)j * ld];
+  if (!isfinite(v.x) || !isfinite(v.y)) atomicOr(flag, 1);
+}
+
+__global__ void diag_real_kernel(const zd* G, int m, int ldg, double* diag) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) diag[k] = G[k + (long)k * ldg].x;
+}
+__global__ void add_diag_kernel(zd* G, int m, int ldg, double sigma) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) G[k + (long)k * ldg].x += sigma;
+}
+
+__device__ inline unsigned long long splitmix64(unsigned long long x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+__device__ inline double u01(unsigned long long x) {  // (0, 1]
+  return ((x >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+}
+__global__ void gaussian_kernel(void* X, long ldx, int rows, int cols, int is_real,
+                                unsigned long long seed) {
+  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)rows * cols) return;
+  int i = (int)(idx % rows), j = (int)(idx / rows);
+  unsigned long long h = splitmix64(seed ^ splitmix64((unsigned long long)idx));
+  double u1 = u01(h), u2 = u01(splitmix64(h));
+  double rad = sqrt(-2.0 * log(u1)), ang = 6.283185307179586 * u2;
+  if (is_real) ((double*)X)[i + (long)j * ldx] = rad * cos(ang);
+  else ((zd*)X)[i + (long)j * ldx] = zmake(rad * cos(ang), rad * sin(ang));
+}
+
+__global__ __launch_bounds__(256) void vec_norm_kernel(const zd* v, int n, double* out) {
+  __shared__ double sh[256];
+  double s = 0;
+  for (int i = threadIdx.x; i < n; i += 256) s += zabs2(v[i]);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sqrt(sh[0]);
+}
+__global__ void vec_scale_kernel(const zd* w, int n, const double* nrm, zd* v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double s = nrm[0] > 0 ? 1.0 / nrm[0] : 0.0;
+  if (i < n) v[i] = zscale(w[i], s);
+}
+
+inline dim3 grid1(long n) { return dim3((unsigned)((n + 255) / 256)); }
+
+}  // namespace
+
+void reduce_partials_hermitian(hipStream_t s, const zd* part, int nparts, int m, zd* G, int ldg) {
+  hipLaunchKernelGGL(reduce_herm_kernel, grid1((long)m * m), dim3(256), 0, s, part, nparts, m, G,
+                     ldg);
+  FEAST_LAUNCH_CHECK();
+}
+
+void cholesky_upper(hipStream_t s, zd* G, int m, int ldg, int* flag, zd* tmp) {
+  (void)tmp;
+  for (int k = 0; k < m; k += CB) {
+    int b = (m - k < CB) ? m - k : CB;
+    zd* Gkk = G + k + (long)k * ldg;
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, s, Gkk, ldg, b, flag);
+    FEAST_LAUNCH_CHECK();
+    int rest = m - k - b;
+    if (rest > 0) {
+      zd* G12 = G + k + (long)(k + b) * ldg;
+      hipLaunchKernelGGL(chol_rowpanel_kernel, dim3((rest + 63) / 64), dim3(256), 0, s, Gkk, ldg,
+                         b, G12, rest);
+      FEAST_LAUNCH_CHECK();
+      zgemm(s, OP_C, OP_N, rest, rest, b, zmake(-1, 0), G12, ldg, G12, ldg, zmake(1, 0),
+            G + (k + b) + (long)(k + b) * ldg, ldg);
+    }
+  }
+}
+
+void upper_inverse(hipStream_t s, const zd* R, int m, int ldr, zd* Rinv, int ldi, zd* tmp) {
+  // Rinv must be zero on entry.  Block columns of 64: Rinv_jj = R_jj^{-1};
+  // Rinv[0:j, j] = -Rinv[0:j, 0:j] (R[0:j, j] Rinv_jj).
+  for (int j = 0; j < m; j += CB) {
+    int b = (m - j < CB) ? m - j : CB;
+    hipLaunchKernelGGL(upper_inv_small_kernel, dim3(1), dim3(256), 0, s, R + j + (long)j * ldr, ldr,
+                       b, Rinv + j + (long)j * ldi, ldi);
+    FEAST_LAUNCH_CHECK();
+    if (j > 0) {
+      zgemm(s, OP_N, OP_N, j, b, b, zmake(1, 0), R + (long)j * ldr, ldr, Rinv + j + (long)j * ldi,
+            ldi, zmake(0, 0), tmp, j);
+      zgemm(s, OP_N, OP_N, j, b, j, zmake(-1, 0), Rinv, ldi, tmp, j, zmake(0, 0),
+            Rinv + (long)j * ldi, ldi);
+    }
+  }
+}
+
+int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* dflag,
+                int max_sweeps) {
+  // work: 3 * mp * mp complex (A ping, A pong, V pong); V is mp x mp.
+  const int mp = m + (m & 1);
+  zd* A0 = work;
+  zd* A1 = work + (long)mp * mp;
+  zd* V1 = work + 2L * mp * mp;
+  hipLaunchKernelGGL(jacobi_init_kernel, grid1((long)mp * mp), dim3(256), 0, s, H, m, mp, A0, V);
+  FEAST_LAUNCH_CHECK();
+  if (mp < 2) {
+    hipLaunchKernelGGL(diag_kernel, dim3(1), dim3(64), 0, s, A0, mp, d);
+    FEAST_LAUNCH_CHECK();
+    return 0;
+  }
+  const long nthreads = (long)(mp / 2) * (mp / 2) + (long)mp * (mp / 2);
+  zd *Ain = A0, *Aout = A1, *Vin = V, *Vout = V1;
+  int sweeps = 0;
+  bool converged = false;
+  for (; sweeps < max_sweeps && !converged; ++sweeps) {
+    for (int r = 0; r < mp - 1; ++r) {
+      hipLaunchKernelGGL(jacobi_round_kernel, grid1(nthreads), dim3(256), 0, s, Ain, Aout, Vin,
+                         Vout, mp, r);
+      FEAST_LAUNCH_CHECK();
+      std::swap(Ain, Aout);
+      std::swap(Vin, Vout);
+    }
+    FEAST_HIP(hipMemsetAsync(dflag, 0, sizeof(int), s));
+    hipLaunchKernelGGL(jacobi_check_kernel, grid1((long)mp * mp), dim3(256), 0, s, Ain, mp, dflag);
+    FEAST_LAUNCH_CHECK();
+    int h = 0;
+    FEAST_HIP(hipMemcpyAsync(&h, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEAST_HIP(hipStreamSynchronize(s));
+    converged = (h == 0);
+  }
+  if (Vin != V) {
+    FEAST_HIP(hipMemcpyAsync(V, Vin, sizeof(zd) * (size_t)mp * mp, hipMemcpyDeviceToDevice, s));
+  }
+  hipLaunchKernelGGL(diag_kernel, grid1(mp), dim3(256), 0, s, Ain, mp, d);
+  FEAST_LAUNCH_CHECK();
+  return converged ? sweeps : -1;
+}
+
+void sort_eigen(hipStream_t s, const double* d, const zd* V, int m, int mp, double* lam, zd* W,
+                int* rank) {
+  hipLaunchKernelGGL(rank_kernel, grid1(mp), dim3(256), 0, s, d, mp, rank);
+  FEAST_LAUNCH_CHECK();
+  hipLaunchKernelGGL(sort_copy_kernel, grid1((long)m * mp), dim3(256), 0, s, d, V, rank, m, mp,
+                     lam, W);
+  FEAST_LAUNCH_CHECK();
+}
+
+void residual_norms(hipStream_t s, const zd* AX, long ldax, const zd* X, long ldx,
+                    const double* lam, int n, int m0, double anorm, double* res) {
+  hipLaunchKernelGGL(residual_kernel, dim3(m0), dim3(256), 0, s, AX, ldax, X, ldx, lam, n, anorm,
+                     res);
+  FEAST_LAUNCH_CHECK();
+}
+
+void copy_matrix(hipStream_t s, const zd* src, long lds, zd* dst, long ldd, int rows, int cols) {
+  hipLaunchKernelGGL(copy_kernel, grid1((long)rows * cols), dim3(256), 0, s, src, lds, dst, ldd,
+                     rows, cols);
+  FEAST_LAUNCH_CHECK();
+}
+void real_to_complex(hipStream_t s, const double* src, long lds, zd* dst, long ldd, int rows,
+                     int cols) {
+  hipLaunchKernelGGL(r2c_kernel, grid1((long)rows * cols), dim3(256), 0, s, src, lds, dst, ldd,
+                     rows, cols);
+  FEAST_LAUNCH_CHECK();
+}
+void complex_to_real(hipStream_t s, const zd* src, long lds, double* dst, long ldd, int rows,
+                     int cols) {
+  hipLaunchKernelGGL(c2r_kernel, grid1((long)rows * cols), dim3(256), 0, s, src, lds, dst, ldd,
+                     rows, cols);
+  FEAST_LAUNCH_CHECK();
+}
+void fill_zero(hipStream_t s, void* p, size_t bytes) { FEAST_HIP(hipMemsetAsync(p, 0, bytes, s)); }
+
+void diag_real(hipStream_t s, const zd* G, int m, int ldg, double* diag) {
+  hipLaunchKernelGGL(diag_real_kernel, grid1(m), dim3(256), 0, s, G, m, ldg, diag);
+  FEAST_LAUNCH_CHECK();
+}
+void add_diag(hipStream_t s, zd* G, int m, int ldg, double sigma) {
+  hipLaunchKernelGGL(add_diag_kernel, grid1(m), dim3(256), 0, s, G, m, ldg, sigma);
+  FEAST_LAUNCH_CHECK();
+}
+void gaussian_fill(hipStream_t s, void* X, long ldx, int rows, int cols, int is_real,
+                   unsigned long long seed) {
+  hipLaunchKernelGGL(gaussian_kernel, grid1((long)rows * cols), dim3(256), 0, s, X, ldx, rows, cols,
+                     is_real, seed);
+  FEAST_LAUNCH_CHECK();
+}
+double norm2_estimate(hipStream_t s, const zd* A, long lda, int n, int iters, zd* work,
+                      double* dnorm) {
+  zd* v = work;
+  zd* w = work + n;
+  gaussian_fill(s, v, n, n, 1, 0, 0x5EEDull);
+  for (int it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL(vec_norm_kernel, dim3(1), dim3(256), 0, s, v, n, dnorm);
+    hipLaunchKernelGGL(vec_scale_kernel, grid1(n), dim3(256), 0, s, v, n, dnorm, v);
+    zgemm(s, OP_N, OP_N, n, 1, n, zmake(1, 0), A, lda, v, n, zmake(0, 0), w, n);
+    std::swap(v, w);
+  }
+  hipLaunchKernelGGL(vec_norm_kernel, dim3(1), dim3(256), 0, s, v, n, dnorm);
+  FEAST_LAUNCH_CHECK();
+  double h = 0;
+  FEAST_HIP(hipMemcpyAsync(&h, dnorm, sizeof(double), hipMemcpyDeviceToHost, s));
+  FEAST_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+int nonfinite_check(hipStream_t s, const zd* a, long ld, int rows, int cols, int* dflag) {
+  FEAST_HIP(hipMemsetAsync(dflag, 0, sizeof(int), s));
+  hipLaunchKernelGGL(nonfinite_kernel, grid1((long)rows * cols), dim3(256), 0, s, a, ld, rows, cols,
+                     dflag);
+  FEAST_LAUNCH_CHECK();
+  int h = 0;
+  FEAST_HIP(hipMemcpyAsync(&h, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+  FEAST_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+}  // namespace feast

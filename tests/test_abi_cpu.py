@@ -1,0 +1,160 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports every function
+declared in include/*.h, and rejects invalid arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1605_08771_amd as fm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(feast_[a-z_0-9]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = fm.lib()
+    names = _declared()
+    assert "feast_solve" in names and "feast_filter_apply" in names
+    assert "feast_rayleigh_ritz" in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    L = fm.lib()
+    for code in (0, 1, 2, 3, 4, 5, 6, -100, -101, -102, -3):
+        assert len(L.feast_status_string(code)) > 0
+
+
+BAD = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+DEV = ctypes.c_void_p(0x2000)
+
+
+def test_filter_apply_argument_checks():
+    L = fm.lib()
+    f = L.feast_filter_apply
+    ok = dict(h=BAD, dt=1, n=10, A=DEV, lda=10, emin=-1.0, emax=1.0, nc=8, prec=0, X=DEV,
+              ldx=10, m0=4, Q=ctypes.c_void_p(0x3000), ldq=10)
+
+    def call(**kw):
+        a = dict(ok)
+        a.update(kw)
+        return f(a["h"], a["dt"], a["n"], a["A"], a["lda"], a["emin"], a["emax"], a["nc"],
+                 a["prec"], a["X"], a["ldx"], a["m0"], a["Q"], a["ldq"])
+
+    assert call(h=None) == -1
+    assert call(dt=7) == -2
+    assert call(n=0) == -3
+    assert call(A=None) == -4
+    assert call(lda=9) == -5
+    assert call(emin=float("nan")) == -6
+    assert call(emin=1.0, emax=1.0) == -7
+    assert call(emin=2.0, emax=1.0) == -7
+    assert call(nc=0) == -8
+    assert call(prec=5) == -9
+    assert call(X=None) == -10
+    assert call(ldx=3) == -11
+    assert call(m0=0) == -12
+    assert call(m0=11) == -12
+    assert call(Q=None) == -13
+    assert call(Q=DEV) == -13  # aliasing X
+    assert call(ldq=1) == -14
+
+
+def test_rayleigh_ritz_argument_checks():
+    L = fm.lib()
+    f = L.feast_rayleigh_ritz
+    lam = (ctypes.c_double * 4)()
+    res = (ctypes.c_double * 4)()
+    m = ctypes.c_int()
+    dp = ctypes.POINTER(ctypes.c_double)
+    args = [BAD, 1, 10, DEV, 10, DEV, 10, 4, -1.0, 1.0, 1.0, ctypes.cast(lam, dp),
+            ctypes.cast(res, dp), ctypes.byref(m)]
+
+    def call(i, v):
+        a = list(args)
+        a[i] = v
+        return f(*a)
+
+    assert call(0, None) == -1
+    assert call(1, 3) == -2
+    assert call(2, -1) == -3
+    assert call(3, None) == -4
+    assert call(4, 2) == -5
+    assert call(5, None) == -6
+    assert call(6, 5) == -7
+    assert call(7, 0) == -8
+    assert call(9, -1.0) == -10
+    assert call(10, 0.0) == -11
+    assert call(11, None) == -12
+    assert call(12, None) == -13
+    assert call(13, None) == -14
+
+
+def test_solve_argument_checks():
+    L = fm.lib()
+    f = L.feast_solve
+    lam = (ctypes.c_double * 8)()
+    res = (ctypes.c_double * 8)()
+    m = ctypes.c_int()
+    it = ctypes.c_int()
+    dp = ctypes.POINTER(ctypes.c_double)
+    good = fm.FeastOpts(n_c=8, m0=4, max_iter=10, refine_max=2, tol=1e-12, anorm=1.0, prec=0,
+                        seed=1)
+
+    def call(opts=good, **kw):
+        a = dict(h=BAD, dt=1, n=10, A=DEV, lda=10, emin=-1.0, emax=1.0, X0=None,
+                 X=ctypes.c_void_p(0x3000), ldx=10)
+        a.update(kw)
+        return f(a["h"], a["dt"], a["n"], a["A"], a["lda"], a["emin"], a["emax"],
+                 ctypes.byref(opts) if opts is not None else None, a["X0"], a["X"], a["ldx"],
+                 ctypes.cast(lam, dp), ctypes.cast(res, dp), ctypes.byref(m), ctypes.byref(it),
+                 None)
+
+    assert call(h=None) == -1
+    assert call(dt=2) == -2
+    assert call(n=0) == -3
+    assert call(A=None) == -4
+    assert call(lda=4) == -5
+    assert call(emax=-2.0) == -7
+    assert call(opts=None) == -8
+    for bad in (dict(n_c=0), dict(m0=0), dict(m0=11), dict(max_iter=0), dict(tol=0.0),
+                dict(prec=9), dict(prec=1, refine_max=0)):
+        o = fm.FeastOpts(n_c=8, m0=4, max_iter=10, refine_max=2, tol=1e-12, anorm=1.0, prec=0,
+                         seed=1)
+        for k, v in bad.items():
+            setattr(o, k, v)
+        assert call(opts=o) == -8, bad
+    assert call(X=None) == -10
+    assert call(ldx=2) == -11
+
+
+def test_kernel_api_argument_checks():
+    L = fm.lib()
+    al = ctypes.cast((ctypes.c_double * 2)(1.0, 0.0), ctypes.POINTER(ctypes.c_double))
+    assert L.feast_kern_gemm(3, 0, 0, 4, 4, 4, al, DEV, 4, DEV, 4, al, DEV, 4, None) == -1
+    assert L.feast_kern_gemm(0, 5, 0, 4, 4, 4, al, DEV, 4, DEV, 4, al, DEV, 4, None) == -2
+    assert L.feast_kern_gemm(0, 0, 0, 4, 4, 4, al, DEV, 3, DEV, 4, al, DEV, 4, None) == -9
+    npo = ctypes.c_int()
+    z = (ctypes.c_double * 2)(0.0, 1.0)
+    assert L.feast_kern_lu(0, DEV, 500, 500, 1, ctypes.cast(z, ctypes.POINTER(ctypes.c_double)),
+                           None, None, ctypes.byref(npo), None) == 0
+    assert npo.value == 512
+    assert L.feast_kern_jacobi(None, 4, None, None, None) == -1
+
+
+def test_binding_rejects_missing_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(fm, "_lib", None)
+    monkeypatch.setattr(fm, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError):
+        fm.lib()

@@ -1,0 +1,126 @@
+"""Kernel-level parity of the HIP building blocks against plain fp64 references on the host:
+the matrix-core complex GEMM (all op combinations, ragged shapes), the batched partial-pivot
+LU of the shifted matrices, and the Jacobi reduced eigensolver."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fe():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need the HIP device"
+    import paper_1605_08771_amd as fm
+    f = fm.Feast()
+    yield f
+    f.close()
+
+
+def _dev(a, dtype=None):
+    import torch
+    import paper_1605_08771_amd as fm
+    t = torch.from_numpy(np.asarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return fm.fortran(t.cuda())
+
+
+def _crand(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+OPS = {0: lambda a: a, 1: lambda a: a.T, 2: lambda a: a.conj().T}
+
+
+@pytest.mark.parametrize("opA", [0, 1, 2])
+@pytest.mark.parametrize("opB", [0, 1, 2])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (17, 5, 33), (64, 64, 16), (130, 77, 70),
+                                   (65, 129, 0), (200, 31, 257)])
+def test_zgemm_fp64(fe, opA, opB, shape):
+    import torch
+    M, N, K = shape
+    rng = np.random.default_rng(M * 1000 + N * 10 + K + 7 * opA + opB)
+    A = _crand(rng, M, K) if opA == 0 else _crand(rng, K, M)
+    B = _crand(rng, K, N) if opB == 0 else _crand(rng, N, K)
+    C = _crand(rng, M, N)
+    alpha, beta = 0.7 - 0.3j, -1.1 + 0.4j
+    ref = alpha * OPS[opA](A) @ OPS[opB](B) + beta * C
+    dA, dB, dC = _dev(A), _dev(B), _dev(C)
+    st = fe.gemm(opA, opB, dA, dB, dC, alpha, beta, M=M, N=N, K=K)
+    torch.cuda.synchronize()
+    assert st == 0
+    got = dC.cpu().numpy()
+    scale = (np.abs(A).max() if A.size else 1) * (np.abs(B).max() if B.size else 1) * max(K, 1)
+    assert np.abs(got - ref).max() <= 1e-14 * scale + 1e-14
+
+
+@pytest.mark.parametrize("opA,opB", [(0, 0), (2, 0), (0, 2)])
+def test_cgemm_fp32(fe, opA, opB):
+    import torch
+    M, N, K = 150, 70, 99
+    rng = np.random.default_rng(11)
+    A = _crand(rng, M, K) if opA == 0 else _crand(rng, K, M)
+    B = _crand(rng, K, N) if opB == 0 else _crand(rng, N, K)
+    C = np.zeros((M, N), dtype=np.complex128)
+    ref = OPS[opA](A) @ OPS[opB](B)
+    dA, dB = _dev(A, torch.complex64), _dev(B, torch.complex64)
+    dC = _dev(C, torch.complex64)
+    assert fe.gemm(opA, opB, dA, dB, dC, 1.0, 0.0, M=M, N=N, K=K) == 0
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy().astype(np.complex128)
+    assert np.abs(got - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
+def test_zgemm_beta_zero_ignores_nan(fe):
+    import torch
+    rng = np.random.default_rng(3)
+    A, B = _crand(rng, 40, 20), _crand(rng, 20, 30)
+    C = np.full((40, 30), np.nan + 1j * np.nan)
+    dA, dB, dC = _dev(A), _dev(B), _dev(C)
+    assert fe.gemm(0, 0, dA, dB, dC, 1.0, 0.0) == 0
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(dC.cpu().numpy(), A @ B, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,prec", [(60, 0), (200, 0), (500, 0), (1030, 0), (300, 1)])
+def test_batched_lu(fe, n, prec):
+    """P_j (z_j I - A) = L_j U_j for every node, with |L| <= 1 (partial pivoting)."""
+    import torch
+    rng = np.random.default_rng(n)
+    G = _crand(rng, n, n)
+    A = 0.5 * (G + G.conj().T) / np.sqrt(n)
+    z = np.array([0.1 + 0.05j, -0.3 + 0.001j, 0.7 + 0.4j])
+    st, LU, perm = fe.lu(_dev(A), z, prec=prec)
+    torch.cuda.synchronize()
+    assert st == 0
+    LU = LU.cpu().numpy().astype(np.complex128)
+    perm = perm.cpu().numpy()
+    np_ = LU.shape[1]
+    eps = np.finfo(np.float64 if prec == 0 else np.float32).eps
+    for j, zj in enumerate(z):
+        M = np.eye(np_, dtype=np.complex128)
+        M[:n, :n] = zj * np.eye(n) - A
+        L = np.tril(LU[j], -1) + np.eye(np_)
+        U = np.triu(LU[j])
+        assert sorted(perm[j]) == list(range(np_))
+        assert np.all(np.abs(L) <= 1 + 1e-6)
+        be = np.linalg.norm(M[perm[j]] - L @ U) / (np.linalg.norm(M) * np_ * eps)
+        assert be < 5.0, (j, be)
+
+
+@pytest.mark.parametrize("m", [1, 2, 7, 64, 75, 301])
+def test_jacobi_vs_lapack(fe, m):
+    import torch
+    rng = np.random.default_rng(m)
+    G = _crand(rng, m, m)
+    H = 0.5 * (G + G.conj().T)
+    sweeps, d, W = fe.jacobi(torch.from_numpy(H).cuda())
+    torch.cuda.synchronize()
+    assert sweeps >= 0
+    d = d.cpu().numpy()
+    W = W.cpu().numpy()
+    scale = np.linalg.norm(H, 2)
+    np.testing.assert_allclose(d, np.linalg.eigvalsh(H), rtol=0, atol=1e-13 * scale)
+    np.testing.assert_allclose(W.conj().T @ W, np.eye(m), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(H @ W, W * d, rtol=0, atol=1e-13 * scale)

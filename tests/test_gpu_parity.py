@@ -1,0 +1,183 @@
+"""Parity of the HIP hot path (called through the C-ABI) with the FP64 CPU oracle on the same
+seeded inputs: filter application (Sec. 1 eq. contour_int_quad), Rayleigh-Ritz (Appendix,
+step 2) and the whole FEAST iteration (Appendix), plus the status codes.
+
+Bars: filtered block to 1e-11 relative (kappa(z_j I - A) u with kappa <= ~300 here);
+eigenvalues |lam_gpu - lam_ref| <= 1e-10 anorm; subspaces (never vectors, which are unique
+only up to phase / rotation in clusters) to sin(theta_max) <= 1e-8; equal counts m."""
+import numpy as np
+import pytest
+
+from paper_1605_08771_amd import gen
+from tests.pins import sin_theta_max
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fe():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need the HIP device"
+    import paper_1605_08771_amd as fm
+    f = fm.Feast()
+    yield f
+    f.close()
+
+
+def _dev(a):
+    import torch
+    import paper_1605_08771_amd as fm
+    return fm.fortran(torch.from_numpy(np.asarray(a)).cuda())
+
+
+def _small_c2(n=1000, tag=20, m0=None):
+    """Config-2 recipe (edge clusters inside and just outside I) at a reduced size."""
+    n_in, edge, out_edge = 40, 8, 20
+    p = gen.config2(n=n, seed_tag=tag, n_in=n_in, n_in_edge=edge, n_out_edge=out_edge,
+                    m0=m0 or 60, n_c=8, max_iter=200)
+    return p
+
+
+@pytest.mark.parametrize("dtype,n,m0", [("r64", 500, 75), ("c128", 333, 29), ("c128", 777, 40)])
+def test_filter_apply_vs_oracle(fe, orc, dtype, n, m0):
+    import torch
+    rng = gen.rng_for([31, n])
+    emin, emax = -0.1, 0.1
+    lam = gen.uniform_spectrum(rng, n, emin, emax)
+    p = gen.make_problem(lam, emin, emax, m0, 8, 1e-12, 10, dtype == "c128", rng)
+    ref = orc.filter_apply(dtype, p.A, emin, emax, 8, p.X0)
+    st, Q = fe.filter_apply(_dev(p.A), _dev(p.X0), emin, emax, 8)
+    torch.cuda.synchronize()
+    assert st == 0
+    got = Q.cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < 1e-11, err
+
+
+def test_filter_apply_diagonal_nodes(fe):
+    """A = diag(lam): Q_ik = rho(lam_i) X_ik with the closed-form rho (nodes and weights)."""
+    import torch
+    from tests.pins import rho_closed
+    lam = np.linspace(-2, 2, 101)
+    n = len(lam)
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
+    for nc in (1, 3, 8, 16):
+        st, Q = fe.filter_apply(_dev(np.diag(lam).astype(complex)), _dev(X), -0.5, 0.7, nc)
+        torch.cuda.synchronize()
+        assert st == 0
+        rho = rho_closed(lam, -0.5, 0.7, nc)
+        np.testing.assert_allclose(Q.cpu().numpy(), rho[:, None] * X, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("dtype", ["r64", "c128"])
+def test_rayleigh_ritz_well_conditioned_vs_oracle(fe, orc, dtype):
+    """On a well-conditioned basis (the Gaussian start block) the Ritz pairs are determined to
+    rounding level: Ritz values equal to 1e-12 anorm, same residuals."""
+    import torch
+    p = gen.config1(n=300, seed_tag=41) if dtype == "r64" else _small_c2(n=400, tag=42)
+    ref = orc.rayleigh_ritz(dtype, p.A, p.X0, p.emin, p.emax, p.anorm)
+    dQ = _dev(p.X0)
+    st, lam, res, m = fe.rayleigh_ritz(_dev(p.A), dQ, p.emin, p.emax, p.anorm)
+    torch.cuda.synchronize()
+    assert st == 0 and ref["status"] == 0
+    assert m == ref["m"]
+    np.testing.assert_allclose(lam, ref["lam"], rtol=0, atol=1e-12 * p.anorm)
+    np.testing.assert_allclose(res, ref["res"], rtol=1e-8, atol=1e-14)
+
+
+@pytest.mark.parametrize("dtype", ["r64", "c128"])
+def test_rayleigh_ritz_filtered_vs_oracle(fe, orc, dtype):
+    """On a filtered block (third FEAST iteration; condition numbers up to ~1e5) the pairs
+    that the subspace resolves (oracle residual < 1e-8) agree to 1e-10 anorm and span the
+    same space; every pair satisfies the Rayleigh-Ritz invariants."""
+    import torch
+    if dtype == "r64":
+        p = gen.config1(n=300, seed_tag=41)
+    else:
+        rng = gen.rng_for([44, 0])
+        lam = gen.uniform_spectrum(rng, 400, -0.1, 0.1)
+        p = gen.make_problem(lam, -0.1, 0.1, 64, 8, 1e-12, 10, True, rng)
+    X2 = orc.feast_solve(dtype, p.A, p.emin, p.emax, 8, p.m0, 1e-30, 2, p.anorm, p.X0)["X"]
+    Q0 = orc.filter_apply(dtype, p.A, p.emin, p.emax, 8, X2)
+    ref = orc.rayleigh_ritz(dtype, p.A, Q0, p.emin, p.emax, p.anorm)
+    dQ = _dev(Q0)
+    st, lam, res, m = fe.rayleigh_ritz(_dev(p.A), dQ, p.emin, p.emax, p.anorm)
+    torch.cuda.synchronize()
+    assert st == 0 and ref["status"] == 0
+    X = dQ.cpu().numpy()
+    np.testing.assert_allclose(X.conj().T @ X, np.eye(p.m0), rtol=0, atol=1e-12)
+    R = p.A @ X - X * lam
+    np.testing.assert_allclose(X.conj().T @ R, 0, rtol=0, atol=1e-12)  # x_j^H r_k = 0
+    np.testing.assert_allclose(res, np.linalg.norm(R, axis=0) / p.anorm, rtol=1e-6, atol=1e-14)
+    good = ref["res"] < 1e-8
+    assert good.sum() >= p.m_true // 2
+    for k in np.where(good)[0]:
+        j = np.argmin(np.abs(lam - ref["lam"][k]))
+        assert abs(lam[j] - ref["lam"][k]) < 1e-10 * p.anorm
+    gi = np.array([np.argmin(np.abs(lam - v)) for v in ref["lam"][good]])
+    assert sin_theta_max(ref["X"][:, good], X[:, gi]) < 1e-6
+
+
+def _check_solve(p, out, ref, dtype):
+    assert out["status"] == 0, out["status"]
+    assert ref["status"] == 0
+    assert out["m"] == ref["m"] == p.m_true
+    sg = (out["lam"] > p.emin) & (out["lam"] < p.emax)
+    so = (ref["lam"] > p.emin) & (ref["lam"] < p.emax)
+    np.testing.assert_allclose(out["lam"][sg], ref["lam"][so], rtol=0, atol=1e-10 * p.anorm)
+    exact = np.sort(p.lam[(p.lam > p.emin) & (p.lam < p.emax)])
+    np.testing.assert_allclose(out["lam"][sg], exact, rtol=0, atol=1e-10 * p.anorm)
+    assert np.max(out["res"][sg]) <= p.tol
+    X = out["X"].cpu().numpy()
+    assert sin_theta_max(ref["X"][:, so], X[:, sg]) < 1e-8
+    ins = (p.lam > p.emin) & (p.lam < p.emax)
+    assert sin_theta_max(p.U[:, ins], X[:, sg]) < 1e-8
+
+
+def test_solve_config1_vs_oracle(fe, orc):
+    """Config 1 at full size: real symmetric n = 500, I = (-0.1, 0.1), m0 = 75, n_c = 8."""
+    import torch
+    p = gen.config1()
+    ref = orc.feast_solve("r64", p.A, p.emin, p.emax, p.n_c, p.m0, p.tol, p.max_iter, p.anorm,
+                          p.X0)
+    out = fe.solve(_dev(p.A), p.emin, p.emax, p.m0, n_c=p.n_c, tol=p.tol, max_iter=p.max_iter,
+                   anorm=p.anorm, X0=_dev(p.X0))
+    torch.cuda.synchronize()
+    _check_solve(p, out, ref, "r64")
+    assert abs(out["iters"] - ref["iters"]) <= 1
+
+
+def test_solve_complex_hard_case_vs_oracle(fe, orc):
+    """Config-2 recipe (clusters within 1e-3 of both endpoints, inside and outside) at n=600."""
+    import torch
+    p = _small_c2(n=600, tag=43, m0=60)
+    ref = orc.feast_solve("c128", p.A, p.emin, p.emax, 8, p.m0, p.tol, 200, p.anorm, p.X0)
+    out = fe.solve(_dev(p.A), p.emin, p.emax, p.m0, n_c=8, tol=p.tol, max_iter=200,
+                   anorm=p.anorm, X0=_dev(p.X0))
+    torch.cuda.synchronize()
+    _check_solve(p, out, ref, "c128")
+    assert abs(out["iters"] - ref["iters"]) <= 2
+
+
+def test_solve_status_codes(fe):
+    import torch
+    rng = gen.rng_for([51, 0])
+    lam = gen.uniform_spectrum(rng, 120, -0.2, 0.2)
+    p = gen.make_problem(lam, -0.2, 0.2, 40, 8, 1e-12, 10, True, rng)
+    A, X0 = _dev(p.A), _dev(p.X0)
+    assert fe.solve(A, -0.2, 0.2, 40, tol=1e-15, max_iter=1, anorm=p.anorm, X0=X0)["status"] == 1
+    assert fe.solve(A, 5.0, 6.0, 40, max_iter=10, anorm=p.anorm, X0=X0)["status"] == 3
+    small = max(1, p.m_true - 3)
+    assert fe.solve(A, -0.2, 0.2, small, max_iter=10, anorm=p.anorm,
+                    X0=_dev(p.X0[:, :small]))["status"] == 2
+    Xz = np.array(p.X0)
+    Xz[:, 5] = 0
+    assert fe.solve(A, -0.2, 0.2, 40, max_iter=10, anorm=p.anorm, X0=_dev(Xz))["status"] == 4
+    An = np.array(p.A)
+    An[7, 3] = np.nan
+    assert fe.solve(_dev(An), -0.2, 0.2, 40, max_iter=10, anorm=p.anorm, X0=X0)["status"] == 5
+    # X0 == NULL: seeded Gaussian start on the device, anorm estimated by power iteration
+    out = fe.solve(A, -0.2, 0.2, 40, max_iter=20, seed=7)
+    torch.cuda.synchronize()
+    assert out["status"] == 0 and out["m"] == p.m_true
