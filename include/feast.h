@@ -62,6 +62,14 @@ typedef struct {
   double anorm;     /* ||A||_2 used to scale residuals; <= 0: estimated by power iteration */
   feast_precision prec;
   unsigned long long seed; /* seeds the Gaussian start block when X0 == NULL */
+  int spurious;     /* 0: step 3 of the paper (every Ritz pair inside I counts);
+                       1: a Ritz pair inside I counts only if its filter Rayleigh quotient
+                       mu_k = Re(x_k^H rho(A) x_k) > 1/2.  For this quadrature
+                       rho(t) - 1/2 = ((1 - t^2)/4) sum_j w_j / |e^{i theta_j} - t|^2 with
+                       t = (lambda - c)/r, so rho > 1/2 exactly on I and a Ritz vector built
+                       from eigenvectors outside I has mu < 1/2.  mu_k is read off the next
+                       iteration's filtered block, so a converged run applies the filter once
+                       more than it runs Rayleigh-Ritz. */
 } feast_opts;
 
 #define FEAST_OK 0
@@ -117,7 +125,8 @@ int feast_rayleigh_ritz(feast_handle h, feast_dtype dt, int n, const void* A, in
  * repeat  Q = rho(A) X_i;  Rayleigh-Ritz on Q;  X_{i+1} = all m0 Ritz vectors  until the
  * largest residual of the Ritz pairs inside I is <= opt->tol.
  *   X: n x m0 output (ldx >= n), may equal X0 only if ldx matches.
- *   lambda[m0], res[m0], *m, *iters: host outputs of the last iterate.
+ *   lambda[m0], res[m0], *m, *iters: host outputs of the last iterate (*m counts the pairs
+ *   inside I that pass the opt->spurious test).
  *   trace: NULL or host array of opt->max_iter doubles; trace[i-1] = largest in-interval
  *   residual after iteration i.
  * Argument positions: h=1 dt=2 n=3 A=4 lda=5 emin=6 emax=7 opt=8 (n_c, m0, max_iter, tol,
@@ -127,6 +136,10 @@ int feast_rayleigh_ritz(feast_handle h, feast_dtype dt, int n, const void* A, in
 int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, double emin,
                 double emax, const feast_opts* opt, const void* X0, void* X, int ldx,
                 double* lambda, double* res, int* m, int* iters, double* trace);
+
+/* mu_k of the Ritz vectors returned by the last feast_solve with opt->spurious = 1 (host
+ * array of m0 doubles).  Returns the number of values written. */
+int feast_get_filter_values(feast_handle h, double* mu, int m0);
 
 /* Phase timings of the last feast_solve / feast_filter_apply / feast_rayleigh_ritz call, in
  * milliseconds measured with HIP events on the handle's stream:

@@ -55,6 +55,7 @@ def lib():
                                      ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                      ctypes.c_double, _dp, ctypes.c_int, _dp, ctypes.c_int,
                                      _dp, _dp, _ip, _ip, _dp]
+        L.or_feast_solve_ex.argtypes = L.or_feast_solve.argtypes + [ctypes.c_int, _dp]
         L.or_num_threads.restype = ctypes.c_int
         L.or_set_num_threads.argtypes = [ctypes.c_int]
         L.or_set_fault.argtypes = [ctypes.c_int]
@@ -157,7 +158,9 @@ def rayleigh_ritz(dtype, A, Q, emin, emax, anorm):
     return dict(status=st, X=Q, lam=lam, res=res, m=m.value)
 
 
-def feast_solve(dtype, A, emin, emax, nc, m0, tol, max_iter, anorm, X0):
+def feast_solve(dtype, A, emin, emax, nc, m0, tol, max_iter, anorm, X0, spurious=False):
+    """spurious=True: only Ritz pairs inside I whose filter Rayleigh quotient exceeds 1/2
+    count (see or_feast_solve_ex); the result then also carries 'mu'."""
     A = _fort(A, dtype)
     X0 = _fort(X0, dtype)
     n = A.shape[0]
@@ -167,8 +170,13 @@ def feast_solve(dtype, A, emin, emax, nc, m0, tol, max_iter, anorm, X0):
     m = ctypes.c_int(0)
     iters = ctypes.c_int(0)
     trace = np.zeros(max_iter)
-    st = lib().or_feast_solve(_dt(dtype), n, _ptr(A), n, emin, emax, nc, m0, tol, max_iter,
-                              anorm, _ptr(X0), n, _ptr(X), n, _ptr(lam), _ptr(res),
-                              ctypes.byref(m), ctypes.byref(iters), _ptr(trace))
-    return dict(status=st, X=X, lam=lam, res=res, m=m.value, iters=iters.value,
-                trace=trace[: iters.value])
+    mu = np.zeros(m0)
+    st = lib().or_feast_solve_ex(_dt(dtype), n, _ptr(A), n, emin, emax, nc, m0, tol, max_iter,
+                                 anorm, _ptr(X0), n, _ptr(X), n, _ptr(lam), _ptr(res),
+                                 ctypes.byref(m), ctypes.byref(iters), _ptr(trace),
+                                 int(spurious), _ptr(mu))
+    out = dict(status=st, X=X, lam=lam, res=res, m=m.value, iters=iters.value,
+               trace=trace[: iters.value])
+    if spurious:
+        out["mu"] = mu
+    return out

@@ -536,11 +536,18 @@ int or_rayleigh_ritz(int dtype, int n, const double* A, int lda, double* Q, int 
 /* Appendix, FEAST algorithm: X' = rho(A) X_i; Rayleigh-Ritz; X_{i+1} = X' W (all m0 Ritz
  * vectors); stop when r = max_{lambda_k in I} res_k <= tol.  Status rules (the paper only
  * states the precondition "fewer than m0 eigenvalues in I"): m >= m0 at iteration >= 2 ->
- * 2; m = 0 at two consecutive iterations -> 3; max_iter reached -> 1.  trace[it-1] = r.    */
-int or_feast_solve(int dtype, int n, const double* A, int lda, double emin, double emax, int nc,
-                   int m0, double tol, int max_iter, double anorm, const double* X0, int ldx0,
-                   double* X, int ldx, double* lambda, double* res, int* m, int* iters,
-                   double* trace) {
+ * 2; m = 0 at two consecutive iterations -> 3; max_iter reached -> 1.  trace[it-1] = r.
+ *
+ * spurious = 1 (an option beyond the paper's step 3): a Ritz pair inside I counts only if
+ * its filter Rayleigh quotient mu_k = Re(x_k^H rho(A) x_k) exceeds 1/2.  For the n_c-point
+ * rule on the circle, rho(t) - 1/2 = ((1 - t^2)/4) sum_j w_j / |e^{i theta_j} - t|^2, so
+ * rho > 1/2 exactly on I; a Ritz vector made of eigenvectors outside I has mu < 1/2.  mu_k is
+ * computed by applying the filter to the Ritz vectors, which is also the next iteration's
+ * step 1.  mu_out (nullable) receives mu of the returned Ritz vectors (spurious = 1).      */
+int or_feast_solve_ex(int dtype, int n, const double* A, int lda, double emin, double emax,
+                      int nc, int m0, double tol, int max_iter, double anorm, const double* X0,
+                      int ldx0, double* X, int ldx, double* lambda, double* res, int* m,
+                      int* iters, double* trace, int spurious, double* mu_out) {
   if (dtype != 0 && dtype != 1) return -1;
   if (n < 1) return -2;
   if (!A) return -3;
@@ -561,6 +568,7 @@ int or_feast_solve(int dtype, int n, const double* A, int lda, double emin, doub
   if (!all_finite(Az, (size_t)n * n)) { free(Az); return 5; }
   zc* Xz = load_matrix(dtype, n, m0, X0, ldx0);
   zc* Qz = malloc(sizeof(zc) * (size_t)n * m0);
+  double* mu = malloc(sizeof(double) * m0);
   factors_t f;
   memset(&f, 0, sizeof(f));
   int st = factors_build(&f, Az, n, emin, emax, nc);
@@ -568,16 +576,30 @@ int or_feast_solve(int dtype, int n, const double* A, int lda, double emin, doub
   *m = 0;
   if (st == 0) {
     st = 1;
+    filter_with_factors(&f, dtype, Xz, m0, Qz); /* step 1 of the first iteration */
     for (it = 1; it <= max_iter; it++) {
-      filter_with_factors(&f, dtype, Xz, m0, Qz); /* step 1 */
       int mm = 0;
       int rst = rr_core(n, Az, Qz, m0, emin, emax, anorm, lambda, res, &mm); /* step 2 */
-      *m = mm;
       memcpy(Xz, Qz, sizeof(zc) * (size_t)n * m0);
-      if (rst != 0) { st = rst; break; }
+      if (rst != 0) { *m = mm; st = rst; break; }
+      filter_with_factors(&f, dtype, Xz, m0, Qz); /* step 1 of the next iteration */
       double r = 0.0; /* step 3 */
-      for (int k = 0; k < m0; k++)
-        if (lambda[k] > emin && lambda[k] < emax && res[k] > r) r = res[k];
+      int cnt = 0;
+      for (int k = 0; k < m0; k++) {
+        if (!(lambda[k] > emin && lambda[k] < emax)) continue;
+        if (spurious) {
+          double d = 0.0;
+          for (int i = 0; i < n; i++)
+            d += creal(conj(Xz[i + (size_t)k * n]) * Qz[i + (size_t)k * n]);
+          mu[k] = d;
+          if (!(d > 0.5)) continue;
+        }
+        cnt++;
+        if (res[k] > r) r = res[k];
+      }
+      if (!spurious) cnt = mm;
+      mm = cnt;
+      *m = mm;
       if (trace) trace[it - 1] = r;
       if (mm == 0) {
         if (prev_m == 0) { st = 3; break; }
@@ -590,11 +612,27 @@ int or_feast_solve(int dtype, int n, const double* A, int lda, double emin, doub
     }
     if (it > max_iter) it = max_iter;
   }
+  if (mu_out && spurious) {
+    for (int k = 0; k < m0; k++) {
+      double d = 0.0;
+      for (int i = 0; i < n; i++) d += creal(conj(Xz[i + (size_t)k * n]) * Qz[i + (size_t)k * n]);
+      mu_out[k] = d;
+    }
+  }
   *iters = it;
   store_matrix(dtype, n, m0, Xz, X, ldx);
   factors_free(&f);
   free(Az);
   free(Xz);
   free(Qz);
+  free(mu);
   return st;
+}
+
+int or_feast_solve(int dtype, int n, const double* A, int lda, double emin, double emax, int nc,
+                   int m0, double tol, int max_iter, double anorm, const double* X0, int ldx0,
+                   double* X, int ldx, double* lambda, double* res, int* m, int* iters,
+                   double* trace) {
+  return or_feast_solve_ex(dtype, n, A, lda, emin, emax, nc, m0, tol, max_iter, anorm, X0, ldx0,
+                           X, ldx, lambda, res, m, iters, trace, 0, NULL);
 }

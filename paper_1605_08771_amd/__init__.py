@@ -30,7 +30,7 @@ class FeastOpts(ctypes.Structure):
     _fields_ = [("n_c", ctypes.c_int), ("m0", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("refine_max", ctypes.c_int), ("tol", ctypes.c_double),
                 ("anorm", ctypes.c_double), ("prec", ctypes.c_int),
-                ("seed", ctypes.c_ulonglong)]
+                ("seed", ctypes.c_ulonglong), ("spurious", ctypes.c_int)]
 
 
 _lib = None
@@ -72,6 +72,7 @@ def lib():
                                   ctypes.c_double, ctypes.c_double, ctypes.POINTER(FeastOpts),
                                   _vp, _vp, ctypes.c_int, _dp, _dp, _ip, _ip, _dp]
         L.feast_get_timings.argtypes = [_vp, _dp, ctypes.c_int]
+        L.feast_get_filter_values.argtypes = [_vp, _dp, ctypes.c_int]
         L.feast_set_profiling.argtypes = [_vp, ctypes.c_int]
         L.feast_get_kernel_stats.argtypes = [_vp, ctypes.c_int, _dp,
                                              ctypes.POINTER(ctypes.c_longlong), _dp]
@@ -176,7 +177,7 @@ class Feast:
         return st, lam, res, m.value
 
     def solve(self, A, emin, emax, m0, n_c=8, tol=1e-12, max_iter=50, anorm=0.0,
-              prec=FEAST_FP64, refine_max=4, X0=None, seed=0, X=None):
+              prec=FEAST_FP64, refine_max=4, X0=None, seed=0, X=None, spurious=False):
         import numpy as np
         import torch
         dt = _dtype_code(A)
@@ -188,7 +189,7 @@ class Feast:
         if X0 is not None and _ld(X0, "X0") != ldx:
             raise ValueError("X0 and X must share the leading dimension")
         opts = FeastOpts(n_c=n_c, m0=m0, max_iter=max_iter, refine_max=refine_max, tol=tol,
-                         anorm=anorm, prec=prec, seed=seed)
+                         anorm=anorm, prec=prec, seed=seed, spurious=int(spurious))
         lam = np.zeros(m0)
         res = np.zeros(m0)
         trace = np.zeros(max_iter)
@@ -199,8 +200,13 @@ class Feast:
                                _vp(X.data_ptr()), ldx, lam.ctypes.data_as(_dp),
                                res.ctypes.data_as(_dp), ctypes.byref(m), ctypes.byref(iters),
                                trace.ctypes.data_as(_dp))
-        return dict(status=st, X=X, lam=lam, res=res, m=m.value, iters=iters.value,
-                    trace=trace[: iters.value])
+        out = dict(status=st, X=X, lam=lam, res=res, m=m.value, iters=iters.value,
+                   trace=trace[: iters.value])
+        if spurious:
+            mu = np.zeros(m0)
+            lib().feast_get_filter_values(self.h, mu.ctypes.data_as(_dp), m0)
+            out["mu"] = mu
+        return out
 
     # ---------------------------------------------------------------- building blocks
     def gemm(self, opA, opB, A, B, C, alpha=1.0, beta=0.0, M=None, N=None, K=None):

@@ -211,7 +211,8 @@ struct feast_ctx {
   Buf b_B, b_Z, b_Xc, b_Qc, b_X0c;
   // Rayleigh-Ritz
   Buf b_Q1, b_Q2, b_AQ, b_AX, b_G, b_part, b_Rinv, b_rrtmp, b_H, b_jac, b_V, b_d, b_lam, b_res,
-      b_rank, b_W, b_flag, b_diag, b_pow;
+      b_rank, b_W, b_flag, b_diag, b_pow, b_mu;
+  std::vector<double> mu;
   PhaseTimer timer;
   KernelProfiler prof;
 };
@@ -527,7 +528,7 @@ int feast_destroy(feast_handle h) {
                  &h->b_omega, &h->b_Ac, &h->b_B, &h->b_Z, &h->b_Xc, &h->b_Qc, &h->b_X0c,
                  &h->b_Q1, &h->b_Q2, &h->b_AQ, &h->b_AX, &h->b_G, &h->b_part, &h->b_Rinv,
                  &h->b_rrtmp, &h->b_H, &h->b_jac, &h->b_V, &h->b_d, &h->b_lam, &h->b_res,
-                 &h->b_rank, &h->b_W, &h->b_flag, &h->b_diag, &h->b_pow};
+                 &h->b_rank, &h->b_W, &h->b_flag, &h->b_diag, &h->b_pow, &h->b_mu};
   for (Buf* b : bufs) b->release();
   delete h;
   return 0;
@@ -726,22 +727,42 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
     }
     st = FEAST_NOT_CONVERGED;
     int it = 0, prev_m = -1, mm = 0;
-    for (it = 1; it <= opt->max_iter; ++it) {
-      int fs = filter_core(h, dt, n, m0, Xw, n, Qf, n);  // step 1
-      if (fs) {
-        st = fs;
-        break;
-      }
+    const bool spur = opt->spurious != 0;
+    h->mu.assign(m0, 0.0);
+    int fs = filter_core(h, dt, n, m0, Xw, n, Qf, n);  // step 1 of the first iteration
+    if (fs) {
+      st = fs;
+      it = 1;
+    }
+    for (it = 1; fs == 0 && it <= opt->max_iter; ++it) {
       int rs = rr_core(h, Ac, ldac, n, Qf, n, m0, emin, emax, anorm, lambda, res, &mm);  // step 2
       std::swap(Xw, Qf);  // Ritz vectors become the next block
-      finish_timing(h);
       if (rs) {
+        finish_timing(h);
         st = rs;
         break;
       }
+      if (spur) {  // the next step 1 gives mu_k = Re(x_k^H rho(A) x_k)
+        fs = filter_core(h, dt, n, m0, Xw, n, Qf, n);
+        if (fs) {
+          st = fs;
+          break;
+        }
+        double* dmu = h->b_mu.get<double>(m0);
+        coldot_re(s, Xw, n, Qf, n, n, m0, dmu);
+        FEAST_HIP(hipMemcpyAsync(h->mu.data(), dmu, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
+        FEAST_HIP(hipStreamSynchronize(s));
+      }
+      finish_timing(h);
       double r = 0;  // step 3
-      for (int k = 0; k < m0; ++k)
-        if (lambda[k] > emin && lambda[k] < emax) r = std::max(r, res[k]);
+      int cnt = 0;
+      for (int k = 0; k < m0; ++k) {
+        if (!(lambda[k] > emin && lambda[k] < emax)) continue;
+        if (spur && !(h->mu[k] > 0.5)) continue;
+        cnt++;
+        r = std::max(r, res[k]);
+      }
+      mm = cnt;
       if (trace) trace[it - 1] = r;
       if (mm == 0) {
         if (prev_m == 0) {
@@ -756,6 +777,13 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
         break;
       }
       prev_m = mm;
+      if (!spur && it < opt->max_iter) {
+        fs = filter_core(h, dt, n, m0, Xw, n, Qf, n);  // step 1 of the next iteration
+        if (fs) {
+          st = fs;
+          break;
+        }
+      }
     }
     if (it > opt->max_iter) it = opt->max_iter;
     *iters = it;
@@ -772,6 +800,13 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
   } catch (const std::bad_alloc&) {
     return FEAST_ERR_ALLOC;
   }
+}
+
+int feast_get_filter_values(feast_handle h, double* mu, int m0) {
+  if (!h || !mu) return 0;
+  int k = std::min(m0, (int)h->mu.size());
+  for (int i = 0; i < k; ++i) mu[i] = h->mu[i];
+  return k;
 }
 
 int feast_get_timings(feast_handle h, double* out, int count) {

@@ -98,6 +98,9 @@ void sort_eigen(hipStream_t s, const double* d, const zd* V, int m, int mp, doub
 // res_k = || AX_k - lam_k X_k ||_2 / anorm.
 void residual_norms(hipStream_t s, const zd* AX, long ldax, const zd* X, long ldx,
                     const double* lam, int n, int m0, double anorm, double* res);
+// out[k] = Re(sum_i conj(X[i,k]) Y[i,k]), k < m0.
+void coldot_re(hipStream_t s, const zd* X, long ldx, const zd* Y, long ldy, int n, int m0,
+               double* out);
 void copy_matrix(hipStream_t s, const zd* src, long lds, zd* dst, long ldd, int rows, int cols);
 void real_to_complex(hipStream_t s, const double* src, long lds, zd* dst, long ldd, int rows,
                      int cols);

@@ -303,6 +303,25 @@ __global__ __launch_bounds__(256) void residual_kernel(const zd* __restrict__ AX
   if (threadIdx.x == 0) res[k] = sqrt(sh[0]) / anorm;
 }
 
+__global__ __launch_bounds__(256) void coldot_kernel(const zd* __restrict__ X, long ldx,
+                                                     const zd* __restrict__ Y, long ldy, int n,
+                                                     double* out) {
+  __shared__ double sh[256];
+  const int k = blockIdx.x;
+  double s = 0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    zd a = X[i + (long)k * ldx], b = Y[i + (long)k * ldy];
+    s += a.x * b.x + a.y * b.y;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = sh[0];
+}
+
 __global__ void copy_kernel(const zd* src, long lds, zd* dst, long ldd, int rows, int cols) {
   long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (idx >= (long)rows * cols) return;
@@ -478,6 +497,12 @@ void residual_norms(hipStream_t s, const zd* AX, long ldax, const zd* X, long ld
                     const double* lam, int n, int m0, double anorm, double* res) {
   hipLaunchKernelGGL(residual_kernel, dim3(m0), dim3(256), 0, s, AX, ldax, X, ldx, lam, n, anorm,
                      res);
+  FEAST_LAUNCH_CHECK();
+}
+
+void coldot_re(hipStream_t s, const zd* X, long ldx, const zd* Y, long ldy, int n, int m0,
+               double* out) {
+  hipLaunchKernelGGL(coldot_kernel, dim3(m0), dim3(256), 0, s, X, ldx, Y, ldy, n, out);
   FEAST_LAUNCH_CHECK();
 }
 

@@ -181,3 +181,27 @@ def test_solve_status_codes(fe):
     out = fe.solve(A, -0.2, 0.2, 40, max_iter=20, seed=7)
     torch.cuda.synchronize()
     assert out["status"] == 0 and out["m"] == p.m_true
+
+
+def test_solve_spurious_pairs_vs_oracle(fe, orc):
+    """Hard case where spurious Ritz values fill I: with the filter Rayleigh-quotient test both
+    sides converge to exactly the eigenvalues inside I, in the same number of iterations (+-3)."""
+    import torch
+    p = gen.config2(n=500, seed_tag=79, n_in=30, n_in_edge=6, n_out_edge=30, m0=50, n_c=8,
+                    max_iter=150)
+    ref = orc.feast_solve("c128", p.A, p.emin, p.emax, 8, p.m0, 1e-12, 150, p.anorm, p.X0,
+                          spurious=True)
+    out = fe.solve(_dev(p.A), p.emin, p.emax, p.m0, n_c=8, tol=1e-12, max_iter=150,
+                   anorm=p.anorm, X0=_dev(p.X0), spurious=True)
+    plain = fe.solve(_dev(p.A), p.emin, p.emax, p.m0, n_c=8, tol=1e-12, max_iter=150,
+                     anorm=p.anorm, X0=_dev(p.X0))
+    torch.cuda.synchronize()
+    assert plain["status"] == 2
+    assert out["status"] == 0 and ref["status"] == 0
+    assert out["m"] == ref["m"] == p.m_true
+    kg = (out["lam"] > p.emin) & (out["lam"] < p.emax) & (out["mu"] > 0.5)
+    ko = (ref["lam"] > p.emin) & (ref["lam"] < p.emax) & (ref["mu"] > 0.5)
+    np.testing.assert_allclose(out["lam"][kg], ref["lam"][ko], rtol=0, atol=1e-10 * p.anorm)
+    np.testing.assert_allclose(out["mu"][kg], ref["mu"][ko], rtol=0, atol=1e-8)
+    assert sin_theta_max(ref["X"][:, ko], out["X"].cpu().numpy()[:, kg]) < 1e-8
+    assert abs(out["iters"] - ref["iters"]) <= 3

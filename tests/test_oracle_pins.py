@@ -344,3 +344,44 @@ def test_pins_catch_planted_mistakes(orc, fault):
         assert not _pins_pass(orc)
     finally:
         orc.set_fault(0)
+
+
+# ---------------------------------------------------------------- spurious-pair test
+@pytest.mark.parametrize("nc", [1, 2, 3, 8, 16])
+def test_filter_half_level_identity(orc, nc):
+    """rho(t) - 1/2 = ((1 - t^2)/4) sum_j w_j / |e^{i th_j} - t|^2 > 0 exactly for |t| < 1:
+    the filter separates I from its complement at the level 1/2."""
+    x, w = np.polynomial.legendre.leggauss(nc)
+    th = 0.5 * np.pi * (1 - x)
+    t = np.concatenate([np.linspace(-3, 3, 601), [-1 + 1e-9, 1 - 1e-9, 1 + 1e-9]])
+    closed = (1 - t ** 2) / 4 * np.sum(w / np.abs(np.exp(1j * th)[None, :] - t[:, None]) ** 2,
+                                       axis=1)
+    Q, X = _diag_filter(orc, t, -1.0, 1.0, nc, "r64")
+    rho = Q[:, 0] / X[:, 0]
+    np.testing.assert_allclose(rho - 0.5, closed, rtol=0, atol=1e-12)
+    inside = np.abs(t) < 1
+    assert np.all(rho[inside] > 0.5) and np.all(rho[~inside & (np.abs(t) > 1)] < 0.5)
+
+
+@pytest.mark.slow
+def test_spurious_pairs_hard_case(orc):
+    """Config-2 recipe at n = 500 (30 eigenvalues in I, 30 within 1e-3 outside each edge,
+    m0 = 50): the paper's step 3 stops with m >= m0 (spurious Ritz values from the outer
+    clusters fill I); counting only pairs with filter Rayleigh quotient > 1/2 converges to
+    exactly the eigenvalues inside I."""
+    p = gen.config2(n=500, seed_tag=79, n_in=30, n_in_edge=6, n_out_edge=30, m0=50, n_c=8,
+                    max_iter=150)
+    plain = orc.feast_solve("c128", p.A, p.emin, p.emax, 8, p.m0, 1e-12, 150, p.anorm, p.X0)
+    assert plain["status"] == 2
+    out = orc.feast_solve("c128", p.A, p.emin, p.emax, 8, p.m0, 1e-12, 150, p.anorm, p.X0,
+                          spurious=True)
+    assert out["status"] == 0 and out["m"] == p.m_true
+    keep = (out["lam"] > p.emin) & (out["lam"] < p.emax) & (out["mu"] > 0.5)
+    exact = np.sort(p.lam[(p.lam > p.emin) & (p.lam < p.emax)])
+    np.testing.assert_allclose(out["lam"][keep], exact, rtol=0, atol=1e-12)
+    ins = (p.lam > p.emin) & (p.lam < p.emax)
+    assert sin_theta_max(p.U[:, ins], out["X"][:, keep]) < 1e-8
+    # each accepted mu equals rho(lambda) of the converged pair
+    from tests.pins import rho_closed
+    np.testing.assert_allclose(out["mu"][keep], rho_closed(out["lam"][keep], p.emin, p.emax, 8),
+                               rtol=0, atol=1e-8)
