@@ -6,15 +6,21 @@
 // every MFMA flop is a useful flop of the 8-flop complex multiply-add.
 //
 // Tiling: 256 threads = 4 wave64s in a 2x2 grid, workgroup tile 64x64 complex outputs,
-// K-tile 16 complex, double-buffered LDS (operands are staged k-major so that lanes 0..15
-// of an MFMA fetch read 16 consecutive entries).  Each wave owns 32x32 outputs (2x2 MFMA
-// blocks).  The MFMA is fed with op(B)^T as its first operand and op(A)^T as its second,
-// so it produces C^T: the lane index then runs along the rows of the column-major C and
-// the epilogue stores 16 consecutive rows per lane group.
+// K-tile 16 complex, double-buffered LDS.  Operands are staged k-major so that lanes 0..15
+// of an MFMA fetch read 16 consecutive entries; LDS rows are padded by one entry so that
+// the transposing stores (k contiguous in HBM, k-major in LDS) hit 16 distinct banks.
+// Each wave owns 32x32 outputs (2x2 MFMA blocks).  The MFMA is fed with op(B)^T as its
+// first operand and op(A)^T as its second, so it produces C^T: the lane index then runs
+// along the rows of the column-major C and the epilogue stores 16 consecutive rows per lane
+// group.
 //
-// Batching: two nested strided batch dimensions (blockIdx.y, blockIdx.z) with their own
-// element strides for A, B and C; split-K reductions and per-node/per-block batches are
-// both expressed this way.
+// Scheduling: the linear workgroup id is remapped so that each of the 8 XCDs receives a
+// contiguous range of output tiles, ordered with the N tiles of one M row adjacent: tiles
+// that read the same rows of op(A) run on the same XCD and share its L2.
+//
+// Batching: two nested strided batch dimensions with their own element strides, and up to
+// two independent problems (own A/B/C pointers, leading dimensions and op(A)) with the same
+// M, N, K in one launch; split-K reductions are a batch dimension over K chunks.
 #include "common.h"
 #include "kernels.h"
 
@@ -24,7 +30,7 @@ thread_local GemmProfiler* g_gemm_prof = nullptr;
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256, PAD = 1;
 
 template <typename T>
 struct CT;
@@ -67,93 +73,97 @@ __device__ __forceinline__ v2 ldc_(const v2* p, bool ok) {
   return v;
 }
 
+template <typename v2>
+struct Args {
+  int M, N, K, tilesM, tilesN, n1, n2, splitk;
+  v2 alpha, beta;
+  const v2* A[2];
+  const v2* B[2];
+  v2* C[2];
+  long lda[2], ldb[2], ldc[2];
+  long sA1, sA2, sB1, sB2, sC1, sC2;
+};
+
+// One output tile of one problem, op(A) = OPA.  (i0, j0) is the tile origin.
 template <typename T, int OPA, int OPB>
-__global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K,
-                                                  typename CT<T>::v2 alpha,
-                                                  typename CT<T>::v2 beta,
-                                                  const typename CT<T>::v2* __restrict__ A,
-                                                  long lda, long sA1, long sA2,
-                                                  const typename CT<T>::v2* __restrict__ B,
-                                                  long ldb, long sB1, long sB2,
-                                                  typename CT<T>::v2* __restrict__ C, long ldc,
-                                                  long sC1, long sC2, int tilesM, int splitk) {
+__device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int prob, int b1,
+                                          int b2, int i0, int j0,
+                                          typename CT<T>::v2 (*As)[BK][BM + PAD],
+                                          typename CT<T>::v2 (*Bs)[BK][BN + PAD]) {
   typedef typename CT<T>::v2 v2;
   typedef typename CT<T>::acc accv;
-  __shared__ v2 As[2][BK][BM];
-  __shared__ v2 Bs[2][BK][BN];
-
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  const int tile = blockIdx.x;
-  const int i0 = (tile % tilesM) * BM, j0 = (tile / tilesM) * BN;
-  A += blockIdx.z * sA2;
-  B += blockIdx.z * sB2;
-  C += blockIdx.y * sC1 + blockIdx.z * sC2;
-  if (splitk == 0) {
-    A += blockIdx.y * sA1;
-    B += blockIdx.y * sB1;
-  } else {  // blockIdx.y selects a K chunk; partial products go to separate C slices
-    const long kb = (long)blockIdx.y * splitk;
-    K = (K - kb < splitk) ? (int)(K - kb) : splitk;
+  const int M = a.M, N = a.N;
+  int K = a.K;
+  const long lda = a.lda[prob], ldb = a.ldb[prob], ldc = a.ldc[prob];
+  const v2* A = a.A[prob] + b2 * a.sA2;
+  const v2* B = a.B[prob] + b2 * a.sB2;
+  v2* C = a.C[prob] + b1 * a.sC1 + b2 * a.sC2;
+  if (a.splitk == 0) {
+    A += b1 * a.sA1;
+    B += b1 * a.sB1;
+  } else {  // b1 selects a K chunk; partial products go to separate C slices
+    const long kb = (long)b1 * a.splitk;
+    K = (K - kb < a.splitk) ? (int)(K - kb) : a.splitk;
     A += (OPA == OP_N) ? kb * lda : kb;
     B += (OPB == OP_N) ? kb : kb * ldb;
   }
 
-  const v2 zero = {T(0), T(0)};
   v2 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
 
-#define FEAST_LOAD_A(R, DST)                                                  \
-  {                                                                           \
-    if (OPA == OP_N) {                                                        \
-      int i = t & 63, k = (t >> 6) + 4 * (R);                                 \
-      int gi = i0 + i, gk = k0 + k;                                           \
-      DST = (gi < M && gk < K) ? A[gi + (long)gk * lda] : zero;               \
-    } else {                                                                  \
-      int k = t & 15, i = (t >> 4) + 16 * (R);                                \
-      int gi = i0 + i, gk = k0 + k;                                           \
-      DST = ldc_<v2, OPA == OP_C>(A + gk + (long)gi * lda, gi < M && gk < K);       \
-    }                                                                         \
+#define FEAST_LOAD_A(R, DST)                                                         \
+  {                                                                                  \
+    if (OPA == OP_N) {                                                               \
+      int i = t & 63, k = (t >> 6) + 4 * (R);                                        \
+      int gi = i0 + i, gk = k0 + k;                                                  \
+      DST = ldc_<v2, false>(A + gi + (long)gk * lda, gi < M && gk < K);              \
+    } else {                                                                         \
+      int k = t & 15, i = (t >> 4) + 16 * (R);                                       \
+      int gi = i0 + i, gk = k0 + k;                                                  \
+      DST = ldc_<v2, OPA == OP_C>(A + gk + (long)gi * lda, gi < M && gk < K);        \
+    }                                                                                \
   }
-#define FEAST_LOAD_B(R, DST)                                                  \
-  {                                                                           \
-    if (OPB == OP_N) {                                                        \
-      int k = t & 15, j = (t >> 4) + 16 * (R);                                \
-      int gj = j0 + j, gk = k0 + k;                                           \
-      DST = (gj < N && gk < K) ? B[gk + (long)gj * ldb] : zero;               \
-    } else {                                                                  \
-      int j = t & 63, k = (t >> 6) + 4 * (R);                                 \
-      int gj = j0 + j, gk = k0 + k;                                           \
-      DST = ldc_<v2, OPB == OP_C>(B + gj + (long)gk * ldb, gj < N && gk < K);       \
-    }                                                                         \
+#define FEAST_LOAD_B(R, DST)                                                         \
+  {                                                                                  \
+    if (OPB == OP_N) {                                                               \
+      int k = t & 15, j = (t >> 4) + 16 * (R);                                       \
+      int gj = j0 + j, gk = k0 + k;                                                  \
+      DST = ldc_<v2, false>(B + gk + (long)gj * ldb, gj < N && gk < K);              \
+    } else {                                                                         \
+      int j = t & 63, k = (t >> 6) + 4 * (R);                                        \
+      int gj = j0 + j, gk = k0 + k;                                                  \
+      DST = ldc_<v2, OPB == OP_C>(B + gj + (long)gk * ldb, gj < N && gk < K);        \
+    }                                                                                \
   }
-#define FEAST_LOAD_TILE(K0)                                                   \
-  {                                                                           \
-    const int k0 = (K0);                                                      \
+#define FEAST_LOAD_TILE(K0)                                                          \
+  {                                                                                  \
+    const int k0 = (K0);                                                             \
     FEAST_LOAD_A(0, ra0) FEAST_LOAD_A(1, ra1) FEAST_LOAD_A(2, ra2) FEAST_LOAD_A(3, ra3) \
     FEAST_LOAD_B(0, rb0) FEAST_LOAD_B(1, rb1) FEAST_LOAD_B(2, rb2) FEAST_LOAD_B(3, rb3) \
   }
-#define FEAST_STORE_AB(R, SA, SB)                                             \
-  {                                                                           \
-    if (OPA == OP_N) As[buf_][(t >> 6) + 4 * (R)][t & 63] = SA;               \
-    else As[buf_][t & 15][(t >> 4) + 16 * (R)] = SA;                          \
-    if (OPB == OP_N) Bs[buf_][t & 15][(t >> 4) + 16 * (R)] = SB;              \
-    else Bs[buf_][(t >> 6) + 4 * (R)][t & 63] = SB;                           \
+#define FEAST_STORE_AB(R, SA, SB)                                                    \
+  {                                                                                  \
+    if (OPA == OP_N) As[buf_][(t >> 6) + 4 * (R)][t & 63] = SA;                      \
+    else As[buf_][t & 15][(t >> 4) + 16 * (R)] = SA;                                 \
+    if (OPB == OP_N) Bs[buf_][t & 15][(t >> 4) + 16 * (R)] = SB;                     \
+    else Bs[buf_][(t >> 6) + 4 * (R)][t & 63] = SB;                                  \
   }
-#define FEAST_STORE_TILE(BUF)                                                 \
-  {                                                                           \
-    const int buf_ = (BUF);                                                   \
-    FEAST_STORE_AB(0, ra0, rb0) FEAST_STORE_AB(1, ra1, rb1)                   \
-    FEAST_STORE_AB(2, ra2, rb2) FEAST_STORE_AB(3, ra3, rb3)                   \
+#define FEAST_STORE_TILE(BUF)                                                        \
+  {                                                                                  \
+    const int buf_ = (BUF);                                                          \
+    FEAST_STORE_AB(0, ra0, rb0) FEAST_STORE_AB(1, ra1, rb1)                          \
+    FEAST_STORE_AB(2, ra2, rb2) FEAST_STORE_AB(3, ra3, rb3)                          \
   }
 
   accv accr[2][2], acci[2][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int p = 0; p < 2; ++p)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      accr[a][b] = accv{T(0), T(0), T(0), T(0)};
-      acci[a][b] = accv{T(0), T(0), T(0), T(0)};
+    for (int q = 0; q < 2; ++q) {
+      accr[p][q] = accv{T(0), T(0), T(0), T(0)};
+      acci[p][q] = accv{T(0), T(0), T(0), T(0)};
     }
 
   const int nkt = (K + BK - 1) / BK;
@@ -186,7 +196,13 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K,
     if (kt + 1 < nkt) FEAST_STORE_TILE(buf ^ 1)
     __syncthreads();
   }
+#undef FEAST_LOAD_A
+#undef FEAST_LOAD_B
+#undef FEAST_LOAD_TILE
+#undef FEAST_STORE_AB
+#undef FEAST_STORE_TILE
 
+  const v2 alpha = a.alpha, beta = a.beta;
   const bool beta_zero = (beta.x == T(0) && beta.y == T(0));
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
@@ -209,56 +225,142 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K,
           C[i + (long)j * ldc] = out;
         }
       }
-#undef FEAST_LOAD_A
-#undef FEAST_LOAD_B
-#undef FEAST_LOAD_TILE
-#undef FEAST_STORE_AB
-#undef FEAST_STORE_TILE
 }
 
-template <typename T, int OPA, int OPB>
-void launch(hipStream_t s, int M, int N, int K, typename CT<T>::v2 alpha,
-            const typename CT<T>::v2* A, long lda, const typename CT<T>::v2* B, long ldb,
-            typename CT<T>::v2 beta, typename CT<T>::v2* C, long ldc, const Batch& bt) {
-  int tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
-  dim3 grid(tm * tn, bt.n1, bt.n2);
-  hipLaunchKernelGGL((gemm_kernel<T, OPA, OPB>), grid, dim3(NT), 0, s, M, N, K, alpha, beta, A,
-                     lda, bt.sA1, bt.sA2, B, ldb, bt.sB1, bt.sB2, C, ldc, bt.sC1, bt.sC2, tm,
-                     bt.splitk);
+template <typename T, int OPA0, int OPA1, int OPB>
+__global__ __launch_bounds__(NT) void gemm_kernel(const Args<typename CT<T>::v2> a) {
+  typedef typename CT<T>::v2 v2;
+  __shared__ v2 As[2][BK][BM + PAD];
+  __shared__ v2 Bs[2][BK][BN + PAD];
+  // XCD-aware order: linear id L runs on XCD L % 8; each XCD gets a contiguous range.
+  const long per = (long)a.tilesM * a.tilesN;
+  const long total = (long)gridDim.x * gridDim.y * gridDim.z;
+  const long L = blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * blockIdx.z);
+  const int x = (int)(L & 7);
+  long start = 0;
+  for (int q = 0; q < x; ++q) start += (total - q + 7) / 8;
+  const long g = start + (L >> 3);
+  const int tile = (int)(g % per);
+  long rest = g / per;
+  const int b1 = (int)(rest % a.n1);
+  rest /= a.n1;
+  const int b2 = (int)(rest % a.n2);
+  const int prob = (int)(rest / a.n2);
+  const int i0 = (tile / a.tilesN) * BM, j0 = (tile % a.tilesN) * BN;
+  if constexpr (OPA0 == OPA1) {
+    gemm_tile<T, OPA0, OPB>(a, prob, b1, b2, i0, j0, As, Bs);
+  } else {
+    if (prob == 0) gemm_tile<T, OPA0, OPB>(a, 0, b1, b2, i0, j0, As, Bs);
+    else gemm_tile<T, OPA1, OPB>(a, 1, b1, b2, i0, j0, As, Bs);
+  }
+}
+
+template <typename T, int OPA0, int OPA1, int OPB>
+void launch(hipStream_t s, const Args<typename CT<T>::v2>& a, int nprob) {
+  dim3 grid(a.tilesM * a.tilesN, a.n1, a.n2 * nprob);
+  hipLaunchKernelGGL((gemm_kernel<T, OPA0, OPA1, OPB>), grid, dim3(NT), 0, s, a);
 }
 
 template <typename T>
-void dispatch(hipStream_t s, int opA, int opB, int M, int N, int K, typename CT<T>::v2 alpha,
-              const typename CT<T>::v2* A, long lda, const typename CT<T>::v2* B, long ldb,
-              typename CT<T>::v2 beta, typename CT<T>::v2* C, long ldc, const Batch& bt) {
-  if (M <= 0 || N <= 0 || bt.n1 <= 0 || bt.n2 <= 0) return;
+void dispatch(hipStream_t s, const int* opA, int nprob, int opB,
+              const Args<typename CT<T>::v2>& a) {
   GemmProfiler* prof = g_gemm_prof;
-  const double flops = 8.0 * M * N * (double)(K > 0 ? K : 0) *
-                       (bt.splitk > 0 ? 1.0 : (double)bt.n1) * bt.n2;
-#define FEAST_G(a, b)                                                                \
-  if (opA == a && opB == b) {                                                       \
-    if (prof) prof->begin(s);                                                       \
-    launch<T, a, b>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);           \
-    FEAST_LAUNCH_CHECK();                                                           \
-    if (prof) prof->end(s, flops);                                                  \
-    return;                                                                         \
+  const double flops = 8.0 * a.M * a.N * (double)(a.K > 0 ? a.K : 0) *
+                       (a.splitk > 0 ? 1.0 : (double)a.n1) * a.n2 * nprob;
+  const int o0 = opA[0], o1 = (nprob == 2) ? opA[1] : opA[0];
+  bool done = false;
+  if (prof) prof->begin(s);
+#define FEAST_G(x, y, b)                                         \
+  if (!done && o0 == x && o1 == y && opB == b) {                 \
+    launch<T, x, y, b>(s, a, nprob);                             \
+    done = true;                                                 \
   }
-  FEAST_G(OP_N, OP_N) FEAST_G(OP_N, OP_T) FEAST_G(OP_N, OP_C)
-  FEAST_G(OP_T, OP_N) FEAST_G(OP_T, OP_T) FEAST_G(OP_T, OP_C)
-  FEAST_G(OP_C, OP_N) FEAST_G(OP_C, OP_T) FEAST_G(OP_C, OP_C)
+  FEAST_G(OP_N, OP_N, OP_N) FEAST_G(OP_N, OP_N, OP_T) FEAST_G(OP_N, OP_N, OP_C)
+  FEAST_G(OP_T, OP_T, OP_N) FEAST_G(OP_T, OP_T, OP_T) FEAST_G(OP_T, OP_T, OP_C)
+  FEAST_G(OP_C, OP_C, OP_N) FEAST_G(OP_C, OP_C, OP_T) FEAST_G(OP_C, OP_C, OP_C)
+  FEAST_G(OP_N, OP_C, OP_N)
 #undef FEAST_G
+  if (!done) throw HipError{hipErrorInvalidValue, "gemm: unsupported op combination"};
+  FEAST_LAUNCH_CHECK();
+  if (prof) prof->end(s, flops);
+}
+
+template <typename v2>
+Args<v2> make_args(int M, int N, int K, v2 alpha, v2 beta, const Batch& bt) {
+  Args<v2> a;
+  a.M = M;
+  a.N = N;
+  a.K = K;
+  a.tilesM = (M + BM - 1) / BM;
+  a.tilesN = (N + BN - 1) / BN;
+  a.n1 = bt.n1;
+  a.n2 = bt.n2;
+  a.splitk = bt.splitk;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.sA1 = bt.sA1;
+  a.sA2 = bt.sA2;
+  a.sB1 = bt.sB1;
+  a.sB2 = bt.sB2;
+  a.sC1 = bt.sC1;
+  a.sC2 = bt.sC2;
+  return a;
+}
+
+template <typename T>
+void gemm1(hipStream_t s, int opA, int opB, int M, int N, int K, typename CT<T>::v2 alpha,
+           const typename CT<T>::v2* A, long lda, const typename CT<T>::v2* B, long ldb,
+           typename CT<T>::v2 beta, typename CT<T>::v2* C, long ldc, const Batch& bt) {
+  if (M <= 0 || N <= 0 || bt.n1 <= 0 || bt.n2 <= 0) return;
+  auto a = make_args(M, N, K, alpha, beta, bt);
+  a.A[0] = a.A[1] = A;
+  a.B[0] = a.B[1] = B;
+  a.C[0] = a.C[1] = C;
+  a.lda[0] = a.lda[1] = lda;
+  a.ldb[0] = a.ldb[1] = ldb;
+  a.ldc[0] = a.ldc[1] = ldc;
+  int ops[1] = {opA};
+  dispatch<T>(s, ops, 1, opB, a);
+}
+
+template <typename T>
+void gemm2(hipStream_t s, int opA0, int opA1, int opB, int M, int N, int K,
+           typename CT<T>::v2 alpha, const typename CT<T>::v2* const A[2], const long lda[2],
+           const typename CT<T>::v2* const B[2], const long ldb[2], typename CT<T>::v2 beta,
+           typename CT<T>::v2* const C[2], const long ldc[2], const Batch& bt) {
+  if (M <= 0 || N <= 0 || bt.n1 <= 0 || bt.n2 <= 0) return;
+  auto a = make_args(M, N, K, alpha, beta, bt);
+  for (int p = 0; p < 2; ++p) {
+    a.A[p] = A[p];
+    a.B[p] = B[p];
+    a.C[p] = C[p];
+    a.lda[p] = lda[p];
+    a.ldb[p] = ldb[p];
+    a.ldc[p] = ldc[p];
+  }
+  int ops[2] = {opA0, opA1};
+  dispatch<T>(s, ops, 2, opB, a);
 }
 
 }  // namespace
 
 void zgemm(hipStream_t s, int opA, int opB, int M, int N, int K, zd alpha, const zd* A, long lda,
            const zd* B, long ldb, zd beta, zd* C, long ldc, const Batch& bt) {
-  dispatch<double>(s, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+  gemm1<double>(s, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
 }
-
 void cgemm(hipStream_t s, int opA, int opB, int M, int N, int K, zf alpha, const zf* A, long lda,
            const zf* B, long ldb, zf beta, zf* C, long ldc, const Batch& bt) {
-  dispatch<float>(s, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+  gemm1<float>(s, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+}
+void zgemm_pair(hipStream_t s, int opA0, int opA1, int opB, int M, int N, int K, zd alpha,
+                const zd* const A[2], const long lda[2], const zd* const B[2], const long ldb[2],
+                zd beta, zd* const C[2], const long ldc[2], const Batch& bt) {
+  gemm2<double>(s, opA0, opA1, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+}
+void cgemm_pair(hipStream_t s, int opA0, int opA1, int opB, int M, int N, int K, zf alpha,
+                const zf* const A[2], const long lda[2], const zf* const B[2], const long ldb[2],
+                zf beta, zf* const C[2], const long ldc[2], const Batch& bt) {
+  gemm2<float>(s, opA0, opA1, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
 }
 
 }  // namespace feast

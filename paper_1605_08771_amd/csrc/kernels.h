@@ -28,6 +28,14 @@ void zgemm(hipStream_t s, int opA, int opB, int M, int N, int K, zd alpha, const
 void cgemm(hipStream_t s, int opA, int opB, int M, int N, int K, zf alpha, const zf* A, long lda,
            const zf* B, long ldb, zf beta, zf* C, long ldc, const Batch& bt = Batch());
 
+// Two problems with equal M, N, K (own pointers, leading dimensions, op(A)) in one launch.
+void zgemm_pair(hipStream_t s, int opA0, int opA1, int opB, int M, int N, int K, zd alpha,
+                const zd* const A[2], const long lda[2], const zd* const B[2], const long ldb[2],
+                zd beta, zd* const C[2], const long ldc[2], const Batch& bt = Batch());
+void cgemm_pair(hipStream_t s, int opA0, int opA1, int opB, int M, int N, int K, zf alpha,
+                const zf* const A[2], const long lda[2], const zf* const B[2], const long ldb[2],
+                zf beta, zf* const C[2], const long ldc[2], const Batch& bt = Batch());
+
 // ---- LU (lu.hip) ---------------------------------------------------------------------
 // Shifted copies M_j = z_j I - A (j < nc) of a real (is_real) or complex n x n matrix into
 // np x np factor storage (ld = np, batch stride np*np); rows/cols n..np-1 set to identity.

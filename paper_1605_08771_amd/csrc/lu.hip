@@ -221,54 +221,66 @@ __global__ __launch_bounds__(RPW) void panel_step_kernel(
   }
 }
 
-// One thread per node: LAPACK-order swap sequence of the panel -> list of row moves
-// (dst <- src) over the affected positions, and the same moves applied to perm.
-__global__ void panel_moves_kernel(int np, int k, int w, const int* pivrows, int* moves,
-                                   int* perm) {
-  if (threadIdx.x != 0) return;
+// One workgroup per node: the LAPACK-order swap sequence of the panel, simulated on the set
+// of affected positions (the panel's top rows and the pivot rows below them), gives a list
+// of row moves (dst <- src) and the same moves applied to perm.  Slots: position k + i is
+// slot i (i < w); the pivot rows below the panel get slots w, w+1, ...
+__global__ __launch_bounds__(128) void panel_moves_kernel(int np, int k, int w,
+                                                          const int* pivrows, int* moves,
+                                                          int* perm) {
+  __shared__ int slot_pos[2 * NBP];   // position held by each slot
+  __shared__ int content[2 * NBP];    // original slot whose row sits at this slot now
+  __shared__ int where_[2 * NBP];     // current slot of each original slot
+  __shared__ int srcp[2 * NBP];
+  __shared__ int pslot[NBP];
+  __shared__ int s_cnt;
   const int node = blockIdx.x;
+  const int t = threadIdx.x;
   const int* pr = pivrows + node * NBP;
-  int pos[2 * NBP], orig[2 * NBP];
-  int cnt = 0;
-  for (int jj = 0; jj < w; ++jj) {
-    pos[cnt] = k + jj;
-    orig[cnt] = k + jj;
-    cnt++;
-  }
-  for (int jj = 0; jj < w; ++jj) {
-    int p = pr[jj];
-    if (p >= k + w) {
-      pos[cnt] = p;
-      orig[cnt] = p;
-      cnt++;
-    }
-  }
-  for (int jj = 0; jj < w; ++jj) {
-    int want = pr[jj];
-    int qa = -1, ta = -1;
-    for (int a = 0; a < cnt; ++a) {
-      if (orig[a] == want) qa = a;
-      if (pos[a] == k + jj) ta = a;
-    }
-    if (qa < 0 || ta < 0) continue;  // only after a reported zero pivot
-    int tmp = orig[ta];
-    orig[ta] = orig[qa];
-    orig[qa] = tmp;
-  }
-  int* mv = moves + node * (4 * NBP + 1);
-  int nm = 0;
   int* pm = perm + (long)node * np;
-  int srcp[2 * NBP];
-  for (int a = 0; a < cnt; ++a) srcp[a] = pm[orig[a]];
-  for (int a = 0; a < cnt; ++a) {
-    if (pos[a] != orig[a]) {
-      mv[1 + 2 * nm] = pos[a];
-      mv[2 + 2 * nm] = orig[a];
-      nm++;
+  if (t == 0) {
+    int cnt = w;
+    for (int jj = 0; jj < w; ++jj) {
+      int p = pr[jj];
+      if (p >= k + w) {
+        slot_pos[cnt] = p;
+        pslot[jj] = cnt++;
+      } else {
+        pslot[jj] = p - k;
+      }
     }
-    pm[pos[a]] = srcp[a];
+    s_cnt = cnt;
   }
-  mv[0] = nm;
+  __syncthreads();
+  const int cnt = s_cnt;
+  if (t < w) slot_pos[t] = k + t;
+  if (t < cnt) {
+    content[t] = t;
+    where_[t] = t;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int jj = 0; jj < w; ++jj) {
+      int src = pslot[jj];
+      if (src < 0 || src >= cnt) continue;  // only after a reported zero pivot
+      int q = where_[src];
+      int a = content[jj], b = content[q];
+      content[jj] = b;
+      content[q] = a;
+      where_[b] = jj;
+      where_[a] = q;
+    }
+  }
+  __syncthreads();
+  int* mv = moves + node * (4 * NBP + 1);
+  if (t < cnt) srcp[t] = pm[slot_pos[content[t]]];
+  __syncthreads();
+  if (t < cnt) {
+    mv[1 + 2 * t] = slot_pos[t];
+    mv[2 + 2 * t] = slot_pos[content[t]];
+    pm[slot_pos[t]] = srcp[t];
+  }
+  if (t == 0) mv[0] = cnt;
 }
 
 constexpr int SWAP_COLS = 32;
@@ -399,7 +411,7 @@ void lu_factor(hipStream_t s, typename V2<T>::t* M, int np, int nc, LuWork& w) {
                          pr[(jj + 1) & 1], w.retired, w.pivrows, w.flag);
       FEAST_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(panel_moves_kernel, dim3(nc), dim3(64), 0, s, np, k, width, w.pivrows,
+    hipLaunchKernelGGL(panel_moves_kernel, dim3(nc), dim3(128), 0, s, np, k, width, w.pivrows,
                        w.moves, w.perm);
     FEAST_LAUNCH_CHECK();
     hipLaunchKernelGGL((laswp_kernel<T>), dim3((np + SWAP_COLS - 1) / SWAP_COLS, nc), dim3(256),

@@ -210,50 +210,83 @@ void tri_inverse(hipStream_t s, const typename V2<T>::t* LU, int np, int nc, int
 }
 
 template <typename T>
+void gemm_pair_t(hipStream_t s, int op0, int op1, int M, int N, int K, double ar,
+                 const typename V2<T>::t* const A[2], const long lda[2],
+                 const typename V2<T>::t* const B[2], const long ldb[2], double br,
+                 typename V2<T>::t* const C[2], const long ldc[2], const Batch& bt);
+template <>
+void gemm_pair_t<double>(hipStream_t s, int op0, int op1, int M, int N, int K, double ar,
+                         const zd* const A[2], const long lda[2], const zd* const B[2],
+                         const long ldb[2], double br, zd* const C[2], const long ldc[2],
+                         const Batch& bt) {
+  zgemm_pair(s, op0, op1, OP_N, M, N, K, zmake(ar, 0), A, lda, B, ldb, zmake(br, 0), C, ldc, bt);
+}
+template <>
+void gemm_pair_t<float>(hipStream_t s, int op0, int op1, int M, int N, int K, double ar,
+                        const zf* const A[2], const long lda[2], const zf* const B[2],
+                        const long ldb[2], double br, zf* const C[2], const long ldc[2],
+                        const Batch& bt) {
+  cgemm_pair(s, op0, op1, OP_N, M, N, K, make_float2((float)ar, 0), A, lda, B, ldb,
+             make_float2((float)br, 0), C, ldc, bt);
+}
+
+// Block sweeps for all (node, side) systems; both sides of a block step share one launch.
+template <typename T>
 void sweeps(hipStream_t s, const typename V2<T>::t* LU, const typename V2<T>::t* invL,
             const typename V2<T>::t* invU, int np, int nc, int nbt, int sides, int m0,
             typename V2<T>::t* B, typename V2<T>::t* Z) {
   typedef typename V2<T>::t v2;
   const int nblk = np / nbt;
   const long per = (long)np * m0;
-  Batch bt;  // over nodes
-  bt.n1 = nc;
-  for (int side = 0; side < sides; ++side) {
-    v2* Bs = B + side * per;
-    v2* Zs = Z + side * per;
-    Batch b = bt;
-    b.sA1 = (long)np * nbt;  // inverse blocks
-    b.sB1 = sides * per;
-    b.sC1 = sides * per;
-    Batch g = bt;
-    g.sA1 = (long)np * np;  // factor
-    g.sB1 = sides * per;
-    g.sC1 = sides * per;
-    // lower sweep: side 0 with L, side 1 with U^H
-    const v2* invLo = (side == 0) ? invL : invU;
-    const int opLo = (side == 0) ? OP_N : OP_C;
-    for (int k = 0; k < nblk; ++k) {
-      const int r0 = k * nbt;
-      gemm_t<T>(s, opLo, OP_N, nbt, m0, nbt, 1.0, invLo + (long)k * nbt * nbt, nbt, Bs + r0, np,
-                0.0, Zs + r0, np, b);
-      const int rest = np - r0 - nbt;
-      if (rest > 0) {
-        const v2* Tb = (side == 0) ? LU + (r0 + nbt) + (long)r0 * np : LU + r0 + (long)(r0 + nbt) * np;
-        gemm_t<T>(s, opLo, OP_N, rest, m0, nbt, -1.0, Tb, np, Zs + r0, np, 1.0, Bs + r0 + nbt, np,
-                  g);
-      }
+  Batch bi;  // inverse blocks x right-hand sides, over nodes
+  bi.n1 = nc;
+  bi.sA1 = (long)np * nbt;
+  bi.sB1 = bi.sC1 = sides * per;
+  Batch bg = bi;  // factor blocks x right-hand sides, over nodes
+  bg.sA1 = (long)np * np;
+  const long ldn[2] = {np, np}, ldb[2] = {nbt, nbt};
+  v2* Bs[2] = {B, B + per};
+  v2* Zs[2] = {Z, Z + per};
+  // lower sweep: side 0 with L, side 1 with U^H (solution into Z)
+  for (int k = 0; k < nblk; ++k) {
+    const int r0 = k * nbt;
+    const v2* iA[2] = {invL + (long)k * nbt * nbt, invU + (long)k * nbt * nbt};
+    const v2* rhs[2] = {Bs[0] + r0, Bs[1] + r0};
+    v2* out[2] = {Zs[0] + r0, Zs[1] + r0};
+    if (sides == 2)
+      gemm_pair_t<T>(s, OP_N, OP_C, nbt, m0, nbt, 1.0, iA, ldb, rhs, ldn, 0.0, out, ldn, bi);
+    else
+      gemm_t<T>(s, OP_N, OP_N, nbt, m0, nbt, 1.0, iA[0], nbt, rhs[0], np, 0.0, out[0], np, bi);
+    const int rest = np - r0 - nbt;
+    if (rest > 0) {
+      const v2* T2[2] = {LU + (r0 + nbt) + (long)r0 * np, LU + r0 + (long)(r0 + nbt) * np};
+      const v2* zin[2] = {Zs[0] + r0, Zs[1] + r0};
+      v2* upd[2] = {Bs[0] + r0 + nbt, Bs[1] + r0 + nbt};
+      if (sides == 2)
+        gemm_pair_t<T>(s, OP_N, OP_C, rest, m0, nbt, -1.0, T2, ldn, zin, ldn, 1.0, upd, ldn, bg);
+      else
+        gemm_t<T>(s, OP_N, OP_N, rest, m0, nbt, -1.0, T2[0], np, zin[0], np, 1.0, upd[0], np,
+                  bg);
     }
-    // upper sweep: side 0 with U, side 1 with L^H; right-hand side Z, solution into B
-    const v2* invUp = (side == 0) ? invU : invL;
-    const int opUp = (side == 0) ? OP_N : OP_C;
-    for (int k = nblk - 1; k >= 0; --k) {
-      const int r0 = k * nbt;
-      gemm_t<T>(s, opUp, OP_N, nbt, m0, nbt, 1.0, invUp + (long)k * nbt * nbt, nbt, Zs + r0, np,
-                0.0, Bs + r0, np, b);
-      if (r0 > 0) {
-        const v2* Tb = (side == 0) ? LU + (long)r0 * np : LU + r0;
-        gemm_t<T>(s, opUp, OP_N, r0, m0, nbt, -1.0, Tb, np, Bs + r0, np, 1.0, Zs, np, g);
-      }
+  }
+  // upper sweep: side 0 with U, side 1 with L^H; right-hand side Z, solution into B
+  for (int k = nblk - 1; k >= 0; --k) {
+    const int r0 = k * nbt;
+    const v2* iA[2] = {invU + (long)k * nbt * nbt, invL + (long)k * nbt * nbt};
+    const v2* rhs[2] = {Zs[0] + r0, Zs[1] + r0};
+    v2* out[2] = {Bs[0] + r0, Bs[1] + r0};
+    if (sides == 2)
+      gemm_pair_t<T>(s, OP_N, OP_C, nbt, m0, nbt, 1.0, iA, ldb, rhs, ldn, 0.0, out, ldn, bi);
+    else
+      gemm_t<T>(s, OP_N, OP_N, nbt, m0, nbt, 1.0, iA[0], nbt, rhs[0], np, 0.0, out[0], np, bi);
+    if (r0 > 0) {
+      const v2* T2[2] = {LU + (long)r0 * np, LU + r0};
+      const v2* yin[2] = {Bs[0] + r0, Bs[1] + r0};
+      v2* upd[2] = {Zs[0], Zs[1]};
+      if (sides == 2)
+        gemm_pair_t<T>(s, OP_N, OP_C, r0, m0, nbt, -1.0, T2, ldn, yin, ldn, 1.0, upd, ldn, bg);
+      else
+        gemm_t<T>(s, OP_N, OP_N, r0, m0, nbt, -1.0, T2[0], np, yin[0], np, 1.0, upd[0], np, bg);
     }
   }
 }
