@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override n (tests only)")
     ap.add_argument("--prec", default="", choices=["", "fp64", "fp32ir"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the run in the other precision")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -120,10 +122,11 @@ def main():
     f = fm.Feast()
     exact_in = np.sort(p.lam[(p.lam > p.emin) & (p.lam < p.emax)])
 
-    def one(tol, max_iter=p.max_iter):
+    def one(tol, max_iter=p.max_iter, pr=None):
         f.invalidate()
         out = f.solve(A, p.emin, p.emax, p.m0, n_c=p.n_c, tol=tol, max_iter=max_iter,
-                      anorm=p.anorm, X0=X0, prec=prec, spurious=True)
+                      anorm=p.anorm, X0=X0, prec=prec if pr is None else pr, spurious=True,
+                      refine_max=0)
         return out
 
     def check(out, tol):
@@ -174,6 +177,25 @@ def main():
     filt_ms = sum(ph["solve_ms"] + ph["accumulate_ms"] for ph in phases)
     alg_filter = alg_solve + sum(iters) * p.n_c * sides * 8.0 * p.n * p.m0
     filter_tflops = alg_filter / (filt_ms * 1e-3) / 1e12 if filt_ms > 0 else 0.0
+    f.set_profiling(False)
+
+    # the other precision on the same input, to the same threshold (mixed vs FP64)
+    other = fm.FEAST_FP64 if prec == fm.FEAST_FP32_IR else fm.FEAST_FP32_IR
+    other_name = "fp64" if other == fm.FEAST_FP64 else "fp32ir"
+    compare = None
+    if not args.no_compare:
+        one(1e-10, pr=other)  # warm-up of the other path's buffers
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o2 = one(1e-10, pr=other)
+        torch.cuda.synchronize()
+        t_other = time.perf_counter() - t0
+        ok2, err2, res2 = check(o2, 1e-10)
+        compare = {"precision": other_name, "time_s": round(t_other, 4), "iterations": o2["iters"],
+                   "correct": ok2, "max_eig_err": err2, "max_residual": res2,
+                   "phase_ms": {k: round(v, 2) for k, v in f.timings().items()},
+                   "speedup_of_value_path": round(t_other / (total / args.steps), 3)}
+        log(f"[bench] {other_name}: {compare}")
     f.close()
 
     cpu = None
@@ -225,6 +247,7 @@ def main():
         "phase_ms_last_step": {k: round(v, 2) for k, v in phases[-1].items()},
         "lu_gemm_tflops": round(lu["dense_flops"] / (lu["ms"] * 1e-3) / 1e12, 2) if lu["ms"] else None,
         "rr_gemm_ms": round(rr["ms"], 2),
+        "other_precision": compare,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

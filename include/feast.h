@@ -57,7 +57,8 @@ typedef struct {
   int n_c;          /* quadrature nodes on the upper half circle (>= 1) */
   int m0;           /* subspace size, more than the number of eigenvalues in I */
   int max_iter;     /* FEAST iterations (>= 1) */
-  int refine_max;   /* FP32_IR: refinement steps per filter application (>= 1) */
+  int refine_max;   /* FP32_IR: classic refinement steps (FP64 residual with A) when the
+                       filter has no Ritz information, i.e. the first iteration (>= 0) */
   double tol;       /* stop when max residual over Ritz values in I <= tol (> 0) */
   double anorm;     /* ||A||_2 used to scale residuals; <= 0: estimated by power iteration */
   feast_precision prec;
@@ -69,7 +70,10 @@ typedef struct {
                        t = (lambda - c)/r, so rho > 1/2 exactly on I and a Ritz vector built
                        from eigenvectors outside I has mu < 1/2.  mu_k is read off the next
                        iteration's filtered block, so a converged run applies the filter once
-                       more than it runs Rayleigh-Ritz. */
+                       more than it runs Rayleigh-Ritz.  FEAST_FP32_IR always applies this
+                       test: FP32 solves leave the strongly damped directions of the filtered
+                       block at the FP32 noise floor, and Rayleigh-Ritz turns that noise into
+                       Ritz pairs inside I with large residuals. */
 } feast_opts;
 
 #define FEAST_OK 0

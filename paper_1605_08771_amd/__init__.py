@@ -202,7 +202,7 @@ class Feast:
                                trace.ctypes.data_as(_dp))
         out = dict(status=st, X=X, lam=lam, res=res, m=m.value, iters=iters.value,
                    trace=trace[: iters.value])
-        if spurious:
+        if spurious or prec == FEAST_FP32_IR:
             mu = np.zeros(m0)
             lib().feast_get_filter_values(self.h, mu.ctypes.data_as(_dp), m0)
             out["mu"] = mu

@@ -211,7 +211,7 @@ struct feast_ctx {
   Buf b_B, b_Z, b_Xc, b_Qc, b_X0c;
   // Rayleigh-Ritz
   Buf b_Q1, b_Q2, b_AQ, b_AX, b_G, b_part, b_Rinv, b_rrtmp, b_H, b_jac, b_V, b_d, b_lam, b_res,
-      b_rank, b_W, b_flag, b_diag, b_pow, b_mu;
+      b_rank, b_W, b_flag, b_diag, b_pow, b_mu, b_Reig, b_Y64, b_AY, b_rho;
   std::vector<double> mu;
   PhaseTimer timer;
   KernelProfiler prof;
@@ -334,14 +334,27 @@ const zd* complex_A(feast_ctx* h, int dt, int n, const void* A, int lda, long* l
   return (const zd*)h->b_Ac.p;
 }
 
+// Ritz information of the block handed to the filter (FEAST loop, iteration >= 2): X are Ritz
+// vectors with values lam (device) and FP64 residual R = A X - X diag(lam) (n x m0, ld n).
+struct RitzInfo {
+  const zd* R;
+  const double* lam;
+};
+
 // Q (n x m0 complex, ldq) = rho(A) X with X n x m0 complex (ldx).  Factors must be ready.
-int filter_core(feast_ctx* h, int dt, int n, int m0, const zd* X, long ldx, zd* Q, long ldq) {
+// FP32_IR: with ritz, the Ritz-seeded correction; without, FP32 solves plus `refine` classic
+// refinement steps whose residuals X - (z I - A) Y are FP64 (A: complex n x n, lda).
+int filter_core(feast_ctx* h, int dt, int n, int m0, const zd* X, long ldx, zd* Q, long ldq,
+                const zd* A = nullptr, long lda = 0, const RitzInfo* ritz = nullptr,
+                int refine = 0) {
   hipStream_t s = h->stream;
   const int np = h->f_np, nc = h->f_nc, nbt = h->f_nbt;
   const int sides = (dt == FEAST_C128) ? 2 : 1;
   const size_t blk = (size_t)nc * sides * np * m0;
   const int* perm = h->luw.perm;
   const int* pinv = h->luw.pinv;
+  const zd* zdev = (const zd*)h->b_z.p;
+  const zd* odev = (const zd*)h->b_omega.p;
   if (h->f_prec == FEAST_FP64) {
     zd* B = h->b_B.get<zd>(blk);
     zd* Z = h->b_Z.get<zd>(blk);
@@ -353,13 +366,70 @@ int filter_core(feast_ctx* h, int dt, int n, int m0, const zd* X, long ldx, zd* 
                        np, nc, nbt, sides, m0, B, Z);
     }
     hipEvent_t e1 = h->timer.mark(s);
-    accumulate(s, B, n, np, m0, nc, sides, (const zd*)h->b_omega.p, pinv, Q, ldq);
+    accumulate(s, B, n, np, m0, nc, sides, odev, pinv, Q, ldq);
     hipEvent_t e2 = h->timer.mark(s);
     h->timer.add(e0, e1, P_SOLVE);
     h->timer.add(e1, e2, P_ACC);
     return 0;
   }
-  return FEAST_ERR_UNSUPPORTED;
+  // FP32 factors
+  zf* B32 = h->b_B.get<zf>(blk);
+  zf* Z32 = h->b_Z.get<zf>(blk);
+  const zf* F = (const zf*)h->b_fac.p;
+  const zf* iL = (const zf*)h->b_invL.p;
+  const zf* iU = (const zf*)h->b_invU.p;
+  auto sweep32 = [&]() {
+    hipEvent_t a = h->timer.mark(s);
+    {
+      ScopedProf sp(h->prof, K_SOLVE);
+      solve_sweeps_f32(s, F, iL, iU, np, nc, nbt, sides, m0, B32, Z32);
+    }
+    hipEvent_t b = h->timer.mark(s);
+    h->timer.add(a, b, P_SOLVE);
+  };
+  if (ritz) {
+    hipEvent_t e0 = h->timer.mark(s);
+    seeded_rhs(s, ritz->R, n, ritz->lam, zdev, perm, n, np, m0, nc, sides, B32);
+    double* rho = h->b_rho.get<double>(m0);
+    filter_values(s, ritz->lam, zdev, odev, nc, m0, rho);
+    hipEvent_t e1 = h->timer.mark(s);
+    h->timer.add(e0, e1, P_REFINE);
+    sweep32();
+    hipEvent_t e2 = h->timer.mark(s);
+    accumulate_mixed(s, X, ldx, rho, B32, n, np, m0, nc, sides, odev, pinv, Q, ldq);
+    hipEvent_t e3 = h->timer.mark(s);
+    h->timer.add(e2, e3, P_ACC);
+    return 0;
+  }
+  gather_rhs_f32(s, X, ldx, n, np, m0, nc, sides, perm, B32);
+  sweep32();
+  if (refine <= 0) {
+    hipEvent_t e2 = h->timer.mark(s);
+    accumulate_mixed(s, nullptr, 0, nullptr, B32, n, np, m0, nc, sides, odev, pinv, Q, ldq);
+    hipEvent_t e3 = h->timer.mark(s);
+    h->timer.add(e2, e3, P_ACC);
+    return 0;
+  }
+  zd* Y = h->b_Y64.get<zd>(blk);
+  zd* AY = h->b_AY.get<zd>(blk);
+  unpermute_to64(s, B32, pinv, n, np, m0, nc, sides, 0, Y);
+  for (int it = 0; it < refine; ++it) {
+    hipEvent_t e0 = h->timer.mark(s);
+    {
+      ScopedProf sp(h->prof, K_REFINE);
+      zgemm(s, OP_N, OP_N, n, nc * sides * m0, n, zmake(1, 0), A, lda, Y, np, zmake(0, 0), AY, np);
+    }
+    refine_rhs(s, X, ldx, Y, AY, zdev, perm, n, np, m0, nc, sides, B32);
+    hipEvent_t e1 = h->timer.mark(s);
+    h->timer.add(e0, e1, P_REFINE);
+    sweep32();
+    unpermute_to64(s, B32, pinv, n, np, m0, nc, sides, 1, Y);
+  }
+  hipEvent_t e2 = h->timer.mark(s);
+  accumulate_plain(s, Y, n, np, m0, nc, sides, odev, Q, ldq);
+  hipEvent_t e3 = h->timer.mark(s);
+  h->timer.add(e2, e3, P_ACC);
+  return 0;
 }
 
 // Q <- Q R^{-1} with G = Q^H Q = R^H R; Q1 (nq x m0 zero-padded rows) -> Q2.
@@ -404,7 +474,8 @@ int cholqr_pass(feast_ctx* h, int n, int m0, const zd* Q1, zd* Q2, double shift_
 
 // Rayleigh-Ritz on Qin (n x m0 complex, ldq); Ritz vectors written back to Qin.
 int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m0, double emin,
-            double emax, double anorm, double* lam_h, double* res_h, int* m_out) {
+            double emax, double anorm, double* lam_h, double* res_h, int* m_out,
+            zd* Reig = nullptr) {
   hipStream_t s = h->stream;
   ScopedProf sp(h->prof, K_RR);
   hipEvent_t e0 = h->timer.mark(s);
@@ -483,6 +554,7 @@ int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m
   zgemm(s, OP_N, OP_N, n, m0, m0, zmake(1, 0), AQ, n, W, m0, zmake(0, 0), AX, n);   // A X
   double* res = h->b_res.get<double>(m0);
   residual_norms(s, AX, n, Q2, n, lam, n, m0, anorm, res);
+  if (Reig) ritz_residual(s, AX, n, Q2, n, lam, n, m0, Reig);
   copy_matrix(s, Q2, n, Qin, ldq, n, m0);
   FEAST_HIP(hipMemcpyAsync(lam_h, lam, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
   FEAST_HIP(hipMemcpyAsync(res_h, res, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
@@ -528,7 +600,8 @@ int feast_destroy(feast_handle h) {
                  &h->b_omega, &h->b_Ac, &h->b_B, &h->b_Z, &h->b_Xc, &h->b_Qc, &h->b_X0c,
                  &h->b_Q1, &h->b_Q2, &h->b_AQ, &h->b_AX, &h->b_G, &h->b_part, &h->b_Rinv,
                  &h->b_rrtmp, &h->b_H, &h->b_jac, &h->b_V, &h->b_d, &h->b_lam, &h->b_res,
-                 &h->b_rank, &h->b_W, &h->b_flag, &h->b_diag, &h->b_pow, &h->b_mu};
+                 &h->b_rank, &h->b_W, &h->b_flag, &h->b_diag, &h->b_pow, &h->b_mu,
+                 &h->b_Reig, &h->b_Y64, &h->b_AY, &h->b_rho};
   for (Buf* b : bufs) b->release();
   delete h;
   return 0;
@@ -601,7 +674,9 @@ int feast_filter_apply(feast_handle h, feast_dtype dt, int n, const void* A, int
       Qc = (zd*)Q;
       ldqc = ldq;
     }
-    st = filter_core(h, dt, n, m0, Xc, ldxc, Qc, ldqc);
+    long ldac = lda;
+    const zd* Ac = (prec == FEAST_FP32_IR) ? complex_A(h, dt, n, A, lda, &ldac) : nullptr;
+    st = filter_core(h, dt, n, m0, Xc, ldxc, Qc, ldqc, Ac, ldac, nullptr, 2);
     if (st == 0 && dt == FEAST_R64) complex_to_real(s, Qc, n, (double*)Q, ldq, n, m0);
     hipEvent_t t1 = h->timer.mark(s);
     h->timer.add(t0, t1, P_TOTAL);
@@ -675,7 +750,7 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
   if (!opt || opt->n_c < 1 || opt->n_c > 128 || opt->m0 < 1 || opt->m0 > n ||
       opt->max_iter < 1 || !(opt->tol > 0) ||
       (opt->prec != FEAST_FP64 && opt->prec != FEAST_FP32_IR) ||
-      (opt->prec == FEAST_FP32_IR && opt->refine_max < 1))
+      (opt->prec == FEAST_FP32_IR && opt->refine_max < 0))
     return -8;
   if (!X) return -10;
   if (ldx < n) return -11;
@@ -727,23 +802,32 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
     }
     st = FEAST_NOT_CONVERGED;
     int it = 0, prev_m = -1, mm = 0;
-    const bool spur = opt->spurious != 0;
+    // FP32 factors leave the filtered block's damped directions (|rho| far below the FP32
+    // noise floor) as noise, which Rayleigh-Ritz turns into Ritz pairs inside I with large
+    // residuals; the filter-value test rejects them, so FP32_IR always applies it.
+    const bool spur = opt->spurious != 0 || opt->prec == FEAST_FP32_IR;
     h->mu.assign(m0, 0.0);
-    int fs = filter_core(h, dt, n, m0, Xw, n, Qf, n);  // step 1 of the first iteration
+    const bool mixed = opt->prec == FEAST_FP32_IR;
+    zd* Reig = mixed ? h->b_Reig.get<zd>((size_t)n * m0) : nullptr;
+    RitzInfo ri{Reig, nullptr};
+    int fs = filter_core(h, dt, n, m0, Xw, n, Qf, n, Ac, ldac, nullptr,
+                         opt->refine_max);  // step 1 of the first iteration
     if (fs) {
       st = fs;
       it = 1;
     }
     for (it = 1; fs == 0 && it <= opt->max_iter; ++it) {
-      int rs = rr_core(h, Ac, ldac, n, Qf, n, m0, emin, emax, anorm, lambda, res, &mm);  // step 2
+      int rs = rr_core(h, Ac, ldac, n, Qf, n, m0, emin, emax, anorm, lambda, res, &mm,
+                       Reig);  // step 2
       std::swap(Xw, Qf);  // Ritz vectors become the next block
+      ri.lam = (const double*)h->b_lam.p;
       if (rs) {
         finish_timing(h);
         st = rs;
         break;
       }
       if (spur) {  // the next step 1 gives mu_k = Re(x_k^H rho(A) x_k)
-        fs = filter_core(h, dt, n, m0, Xw, n, Qf, n);
+        fs = filter_core(h, dt, n, m0, Xw, n, Qf, n, Ac, ldac, mixed ? &ri : nullptr);
         if (fs) {
           st = fs;
           break;
@@ -778,7 +862,8 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
       }
       prev_m = mm;
       if (!spur && it < opt->max_iter) {
-        fs = filter_core(h, dt, n, m0, Xw, n, Qf, n);  // step 1 of the next iteration
+        fs = filter_core(h, dt, n, m0, Xw, n, Qf, n, Ac, ldac,
+                         mixed ? &ri : nullptr);  // step 1 of the next iteration
         if (fs) {
           st = fs;
           break;

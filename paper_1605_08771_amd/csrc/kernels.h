@@ -89,6 +89,21 @@ void solve_sweeps_f32(hipStream_t s, const zf* LU, const zf* invL, const zf* inv
 void accumulate(hipStream_t s, const zd* Y, int n, int np, int m0, int nc, int sides,
                 const zd* omega_dev, const int* pinv, zd* Q, long ldq);
 
+// ---- mixed precision (mixed.hip) -------------------------------------------------------
+void seeded_rhs(hipStream_t s, const zd* R, long ldr, const double* lam, const zd* z,
+                const int* perm, int n, int np, int m0, int nc, int sides, zf* B);
+void filter_values(hipStream_t s, const double* lam, const zd* z, const zd* omega, int nc, int m0,
+                   double* rho);
+void accumulate_mixed(hipStream_t s, const zd* X, long ldx, const double* rho, const zf* D, int n,
+                      int np, int m0, int nc, int sides, const zd* omega, const int* pinv, zd* Q,
+                      long ldq);
+void unpermute_to64(hipStream_t s, const zf* D, const int* pinv, int n, int np, int m0, int nc,
+                    int sides, int add, zd* Y);
+void refine_rhs(hipStream_t s, const zd* X, long ldx, const zd* Y, const zd* AY, const zd* z,
+                const int* perm, int n, int np, int m0, int nc, int sides, zf* B);
+void accumulate_plain(hipStream_t s, const zd* Y, int n, int np, int m0, int nc, int sides,
+                      const zd* omega, zd* Q, long ldq);
+
 // ---- Rayleigh-Ritz helpers (rr.hip) -------------------------------------------------------
 void reduce_partials_hermitian(hipStream_t s, const zd* part, int nparts, int m, zd* G, int ldg);
 // Blocked Cholesky G = R^H R (upper R, in place, ld = ldg); *flag set on breakdown.
@@ -103,6 +118,9 @@ int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* df
 // Stable ascending sort of d; Wout = V[:, order] (first m columns), lam = d[order].
 void sort_eigen(hipStream_t s, const double* d, const zd* V, int m, int mp, double* lam, zd* W,
                 int* rank);
+// R = AX - X diag(lam) (n x m0, ld n).
+void ritz_residual(hipStream_t s, const zd* AX, long ldax, const zd* X, long ldx,
+                   const double* lam, int n, int m0, zd* R);
 // res_k = || AX_k - lam_k X_k ||_2 / anorm.
 void residual_norms(hipStream_t s, const zd* AX, long ldax, const zd* X, long ldx,
                     const double* lam, int n, int m0, double anorm, double* res);

@@ -322,6 +322,15 @@ __global__ __launch_bounds__(256) void coldot_kernel(const zd* __restrict__ X, l
   if (threadIdx.x == 0) out[k] = sh[0];
 }
 
+__global__ void ritz_residual_kernel(const zd* AX, long ldax, const zd* X, long ldx,
+                                     const double* lam, int n, int m0, zd* R) {
+  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)n * m0) return;
+  int i = (int)(idx % n), k = (int)(idx / n);
+  zd a = AX[i + (long)k * ldax], x = X[i + (long)k * ldx];
+  R[i + (long)k * n] = zmake(a.x - lam[k] * x.x, a.y - lam[k] * x.y);
+}
+
 __global__ void copy_kernel(const zd* src, long lds, zd* dst, long ldd, int rows, int cols) {
   long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (idx >= (long)rows * cols) return;
@@ -503,6 +512,13 @@ void residual_norms(hipStream_t s, const zd* AX, long ldax, const zd* X, long ld
 void coldot_re(hipStream_t s, const zd* X, long ldx, const zd* Y, long ldy, int n, int m0,
                double* out) {
   hipLaunchKernelGGL(coldot_kernel, dim3(m0), dim3(256), 0, s, X, ldx, Y, ldy, n, out);
+  FEAST_LAUNCH_CHECK();
+}
+
+void ritz_residual(hipStream_t s, const zd* AX, long ldax, const zd* X, long ldx,
+                   const double* lam, int n, int m0, zd* R) {
+  hipLaunchKernelGGL(ritz_residual_kernel, grid1((long)n * m0), dim3(256), 0, s, AX, ldax, X, ldx,
+                     lam, n, m0, R);
   FEAST_LAUNCH_CHECK();
 }
 

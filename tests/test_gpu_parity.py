@@ -119,11 +119,13 @@ def test_rayleigh_ritz_filtered_vs_oracle(fe, orc, dtype):
     assert sin_theta_max(ref["X"][:, good], X[:, gi]) < 1e-6
 
 
-def _check_solve(p, out, ref, dtype):
+def _check_solve(p, out, ref, dtype, accept=None):
     assert out["status"] == 0, out["status"]
     assert ref["status"] == 0
     assert out["m"] == ref["m"] == p.m_true
     sg = (out["lam"] > p.emin) & (out["lam"] < p.emax)
+    if accept is not None:
+        sg &= accept
     so = (ref["lam"] > p.emin) & (ref["lam"] < p.emax)
     np.testing.assert_allclose(out["lam"][sg], ref["lam"][so], rtol=0, atol=1e-10 * p.anorm)
     exact = np.sort(p.lam[(p.lam > p.emin) & (p.lam < p.emax)])
@@ -205,3 +207,73 @@ def test_solve_spurious_pairs_vs_oracle(fe, orc):
     np.testing.assert_allclose(out["mu"][kg], ref["mu"][ko], rtol=0, atol=1e-8)
     assert sin_theta_max(ref["X"][:, ko], out["X"].cpu().numpy()[:, kg]) < 1e-8
     assert abs(out["iters"] - ref["iters"]) <= 3
+
+
+# ---------------------------------------------------------------- mixed precision (FP32 factors)
+@pytest.mark.parametrize("dtype,n,m0", [("r64", 500, 75), ("c128", 777, 40)])
+def test_filter_apply_mixed_vs_oracle(fe, orc, dtype, n, m0):
+    """FP32 factors + two FP64-residual refinement steps reach the FP64 filtered block."""
+    import torch
+    import paper_1605_08771_amd as fm
+    rng = gen.rng_for([32, n])
+    emin, emax = -0.1, 0.1
+    lam = gen.uniform_spectrum(rng, n, emin, emax)
+    p = gen.make_problem(lam, emin, emax, m0, 8, 1e-12, 10, dtype == "c128", rng)
+    ref = orc.filter_apply(dtype, p.A, emin, emax, 8, p.X0)
+    fe.invalidate()
+    st, Q = fe.filter_apply(_dev(p.A), _dev(p.X0), emin, emax, 8, prec=fm.FEAST_FP32_IR)
+    torch.cuda.synchronize()
+    fe.invalidate()
+    assert st == 0
+    err = np.abs(Q.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err < 1e-11, err
+
+
+def test_solve_mixed_config1_vs_oracle(fe, orc):
+    """Config 1 (real symmetric n = 500) with FP32 factors: FP64-accurate result."""
+    import torch
+    import paper_1605_08771_amd as fm
+    p = gen.config1()
+    ref = orc.feast_solve("r64", p.A, p.emin, p.emax, p.n_c, p.m0, p.tol, p.max_iter, p.anorm,
+                          p.X0)
+    fe.invalidate()
+    out = fe.solve(_dev(p.A), p.emin, p.emax, p.m0, n_c=p.n_c, tol=p.tol, max_iter=p.max_iter,
+                   anorm=p.anorm, X0=_dev(p.X0), prec=fm.FEAST_FP32_IR, refine_max=0)
+    torch.cuda.synchronize()
+    fe.invalidate()
+    _check_solve(p, out, ref, "r64", accept=out["mu"] > 0.5)
+
+
+def test_solve_mixed_hard_case_vs_oracle(fe, orc):
+    """Config-2 recipe at n = 600 with FP32 factors and the Ritz-seeded correction."""
+    import torch
+    import paper_1605_08771_amd as fm
+    p = _small_c2(n=600, tag=43, m0=60)
+    ref = orc.feast_solve("c128", p.A, p.emin, p.emax, 8, p.m0, p.tol, 200, p.anorm, p.X0)
+    fe.invalidate()
+    out = fe.solve(_dev(p.A), p.emin, p.emax, p.m0, n_c=8, tol=p.tol, max_iter=200,
+                   anorm=p.anorm, X0=_dev(p.X0), prec=fm.FEAST_FP32_IR, refine_max=0)
+    torch.cuda.synchronize()
+    fe.invalidate()
+    _check_solve(p, out, ref, "c128", accept=out["mu"] > 0.5)
+
+
+def test_solve_mixed_spurious_vs_oracle(fe, orc):
+    """Hard case with spurious Ritz values, FP32 factors: same eigenpairs as the FP64 oracle."""
+    import torch
+    import paper_1605_08771_amd as fm
+    p = gen.config2(n=500, seed_tag=79, n_in=30, n_in_edge=6, n_out_edge=30, m0=50, n_c=8,
+                    max_iter=150)
+    ref = orc.feast_solve("c128", p.A, p.emin, p.emax, 8, p.m0, 1e-12, 150, p.anorm, p.X0,
+                          spurious=True)
+    fe.invalidate()
+    out = fe.solve(_dev(p.A), p.emin, p.emax, p.m0, n_c=8, tol=1e-12, max_iter=150,
+                   anorm=p.anorm, X0=_dev(p.X0), spurious=True, prec=fm.FEAST_FP32_IR,
+                   refine_max=0)
+    torch.cuda.synchronize()
+    fe.invalidate()
+    assert out["status"] == 0 and out["m"] == ref["m"] == p.m_true
+    kg = (out["lam"] > p.emin) & (out["lam"] < p.emax) & (out["mu"] > 0.5)
+    ko = (ref["lam"] > p.emin) & (ref["lam"] < p.emax) & (ref["mu"] > 0.5)
+    np.testing.assert_allclose(out["lam"][kg], ref["lam"][ko], rtol=0, atol=1e-10 * p.anorm)
+    assert sin_theta_max(ref["X"][:, ko], out["X"].cpu().numpy()[:, kg]) < 1e-8
