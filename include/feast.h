@@ -87,8 +87,10 @@ typedef struct {
 #define FEAST_ERR_HIP (-101)
 #define FEAST_ERR_UNSUPPORTED (-102)
 
-/* Create a handle on the current HIP device.  hip_stream: a hipStream_t to run on, or NULL
- * for the null stream.  Returns 0 or -1 (h NULL) / FEAST_ERR_HIP. */
+/* Create a handle on the current HIP device.  hip_stream: a hipStream_t to run on, or NULL:
+ * the handle then creates its own blocking stream (ordered with the legacy null stream, so
+ * work the caller queued there completes first).  Every entry point synchronises its stream
+ * before returning.  Returns 0 or -1 (h NULL) / FEAST_ERR_HIP. */
 int feast_create(feast_handle* h, void* hip_stream);
 /* Release all workspace of h.  Safe on NULL. */
 int feast_destroy(feast_handle h);
@@ -96,7 +98,8 @@ int feast_destroy(feast_handle h);
 const char* feast_status_string(int status);
 /* Text of the last HIP error seen by h (empty if none). */
 const char* feast_last_error(feast_handle h);
-/* Drop the cached factorizations (call after modifying A in place). */
+/* Drop the cached factorizations (call after modifying A in place); also those of the batch
+ * workers. */
 void feast_invalidate(feast_handle h);
 
 /* Step 1 of the FEAST algorithm (Appendix) with the quadrature of Sec. 1 eq.
@@ -141,6 +144,33 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
                 double emax, const feast_opts* opt, const void* X0, void* X, int ldx,
                 double* lambda, double* res, int* m, int* iters, double* trace);
 
+/* One problem of a batch (device arrays owned by the caller, host outputs as in feast_solve).
+ * X0 may be NULL (seeded Gaussian start); X0 and X share ldx. */
+typedef struct {
+  int n, lda, ldx, m0;
+  const void* A;
+  double emin, emax;
+  double anorm;      /* <= 0: estimated */
+  const void* X0;
+  void* X;
+  double* lambda;    /* host, m0 */
+  double* res;       /* host, m0 */
+  int* m;            /* host */
+  int* iters;        /* host */
+  int* status;       /* host: the feast_solve return code of this problem */
+} feast_problem;
+
+/* Independent FEAST problems (Sec. 1: disjoint intervals, or independent matrices, are solved
+ * independently and in parallel).  Problems are ordered by decreasing n^3 (largest first)
+ * and handed to nstreams workers, each with its own HIP stream (default priority) and its own
+ * workspace, so small problems overlap on the device.  opt supplies n_c, max_iter, tol, prec,
+ * refine_max, spurious and seed; m0 and anorm come from each problem.
+ * Argument positions: h=1 dt=2 nprob=3 probs=4 opt=5 nstreams=6 (1..32).
+ * Returns 0 when every problem returned FEAST_OK, else the number of problems that did not
+ * (their own codes are in *status). */
+int feast_solve_batched(feast_handle h, feast_dtype dt, int nprob, const feast_problem* probs,
+                        const feast_opts* opt, int nstreams);
+
 /* mu_k of the Ritz vectors returned by the last feast_solve with opt->spurious = 1 (host
  * array of m0 doubles).  Returns the number of values written. */
 int feast_get_filter_values(feast_handle h, double* mu, int m0);
@@ -156,7 +186,8 @@ int feast_get_timings(feast_handle h, double* out, int count);
  * events on the handle's stream and attributed to a class.  Classes: 0 LU trailing update,
  * 1 triangular-solve sweeps, 2 Rayleigh-Ritz, 3 refinement residual, 4 other.
  * feast_get_kernel_stats returns total kernel milliseconds, launch count and dense GEMM
- * flops (8 M N K per complex product) accumulated since profiling was enabled. */
+ * flops (8 M N K per complex product) accumulated since profiling was enabled, summed over h
+ * and its batch workers (whose kernels overlap in time). */
 int feast_set_profiling(feast_handle h, int on);
 int feast_get_kernel_stats(feast_handle h, int kclass, double* total_ms, long long* launches,
                            double* dense_flops);

@@ -33,6 +33,15 @@ class FeastOpts(ctypes.Structure):
                 ("seed", ctypes.c_ulonglong), ("spurious", ctypes.c_int)]
 
 
+class FeastProblem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("lda", ctypes.c_int), ("ldx", ctypes.c_int),
+                ("m0", ctypes.c_int), ("A", ctypes.c_void_p), ("emin", ctypes.c_double),
+                ("emax", ctypes.c_double), ("anorm", ctypes.c_double), ("X0", ctypes.c_void_p),
+                ("X", ctypes.c_void_p), ("lambda_", ctypes.POINTER(ctypes.c_double)),
+                ("res", ctypes.POINTER(ctypes.c_double)), ("m", ctypes.POINTER(ctypes.c_int)),
+                ("iters", ctypes.POINTER(ctypes.c_int)), ("status", ctypes.POINTER(ctypes.c_int))]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -73,6 +82,9 @@ def lib():
                                   _vp, _vp, ctypes.c_int, _dp, _dp, _ip, _ip, _dp]
         L.feast_get_timings.argtypes = [_vp, _dp, ctypes.c_int]
         L.feast_get_filter_values.argtypes = [_vp, _dp, ctypes.c_int]
+        L.feast_solve_batched.argtypes = [_vp, ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(FeastProblem), ctypes.POINTER(FeastOpts),
+                                          ctypes.c_int]
         L.feast_set_profiling.argtypes = [_vp, ctypes.c_int]
         L.feast_get_kernel_stats.argtypes = [_vp, ctypes.c_int, _dp,
                                              ctypes.POINTER(ctypes.c_longlong), _dp]
@@ -207,6 +219,44 @@ class Feast:
             lib().feast_get_filter_values(self.h, mu.ctypes.data_as(_dp), m0)
             out["mu"] = mu
         return out
+
+    def solve_batched(self, problems, n_c=8, tol=1e-12, max_iter=200, prec=FEAST_FP64,
+                      refine_max=0, spurious=False, nstreams=8):
+        """problems: list of dicts with A, emin, emax, m0 and optional anorm, X0 (device,
+        column-major, one dtype for all).  Returns (count_not_ok, list of result dicts)."""
+        import numpy as np
+        import torch
+        if not problems:
+            return 0, []
+        dt = _dtype_code(problems[0]["A"])
+        arr = (FeastProblem * len(problems))()
+        keep = []
+        outs = []
+        for i, pr in enumerate(problems):
+            A = pr["A"]
+            n = A.shape[0]
+            m0 = pr["m0"]
+            X = fortran(torch.empty((n, m0), dtype=A.dtype, device=A.device))
+            lam, res = np.zeros(m0), np.zeros(m0)
+            m, it, st = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(-999)
+            X0 = pr.get("X0")
+            arr[i] = FeastProblem(n=n, lda=_ld(A, "A"), ldx=_ld(X, "X"), m0=m0,
+                                  A=A.data_ptr(), emin=pr["emin"], emax=pr["emax"],
+                                  anorm=pr.get("anorm", 0.0),
+                                  X0=X0.data_ptr() if X0 is not None else None,
+                                  X=X.data_ptr(), lambda_=lam.ctypes.data_as(_dp),
+                                  res=res.ctypes.data_as(_dp), m=ctypes.pointer(m),
+                                  iters=ctypes.pointer(it), status=ctypes.pointer(st))
+            keep += [X, lam, res, m, it, st]
+            outs.append((X, lam, res, m, it, st))
+        opts = FeastOpts(n_c=n_c, m0=1, max_iter=max_iter, refine_max=refine_max, tol=tol,
+                         anorm=0.0, prec=prec, seed=0, spurious=int(spurious))
+        torch.cuda.synchronize()
+        bad = lib().feast_solve_batched(self.h, dt, len(problems), arr, ctypes.byref(opts),
+                                        nstreams)
+        results = [dict(status=st.value, X=X, lam=lam, res=res, m=m.value, iters=it.value)
+                   for (X, lam, res, m, it, st) in outs]
+        return bad, results
 
     # ---------------------------------------------------------------- building blocks
     def gemm(self, opA, opB, A, B, C, alpha=1.0, beta=0.0, M=None, N=None, K=None):

@@ -2,7 +2,9 @@
 // the FEAST loop (Appendix, FEAST algorithm).  Host code only orchestrates launches on the
 // handle's stream; every arithmetic step of the path runs in this library's kernels.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <thread>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -192,6 +194,7 @@ struct ScopedProf {
 
 struct feast_ctx {
   hipStream_t stream = nullptr;
+  bool own_stream = false;
   int device = 0;
   std::string last_error;
   // factor cache
@@ -215,6 +218,10 @@ struct feast_ctx {
   std::vector<double> mu;
   PhaseTimer timer;
   KernelProfiler prof;
+  JacobiGraph jgraph;
+  // batched workers (each with its own stream and workspace)
+  std::vector<feast_ctx*> workers;
+  std::vector<hipStream_t> worker_streams;
 };
 
 namespace {
@@ -543,7 +550,7 @@ int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m
   zd* V = h->b_V.get<zd>((size_t)mp * mp);
   zd* jw = h->b_jac.get<zd>(3 * (size_t)mp * mp);
   int* dflag = h->b_flag.get<int>(64);
-  int sweeps = jacobi_eigh(s, H, m0, d, V, jw, dflag, 40);
+  int sweeps = jacobi_eigh(s, H, m0, d, V, jw, dflag, 40, &h->jgraph);
   (void)sweeps;
   double* lam = h->b_lam.get<double>(mp);
   zd* W = h->b_W.get<zd>((size_t)m0 * m0);
@@ -589,6 +596,14 @@ int feast_create(feast_handle* out, void* hip_stream) {
     *out = nullptr;
     return FEAST_ERR_HIP;
   }
+  if (!h->stream) {  // own blocking stream: ordered with the legacy default stream
+    if (hipStreamCreate(&h->stream) != hipSuccess) {
+      delete h;
+      *out = nullptr;
+      return FEAST_ERR_HIP;
+    }
+    h->own_stream = true;
+  }
   *out = h;
   return 0;
 }
@@ -596,6 +611,11 @@ int feast_create(feast_handle* out, void* hip_stream) {
 int feast_destroy(feast_handle h) {
   if (!h) return 0;
   (void)hipStreamSynchronize(h->stream);
+  for (size_t w = 0; w < h->workers.size(); ++w) {
+    feast_destroy(h->workers[w]);
+    (void)hipStreamDestroy(h->worker_streams[w]);
+  }
+  h->workers.clear();
   Buf* bufs[] = {&h->b_fac, &h->b_invL, &h->b_invU, &h->b_tri_tmp, &h->b_luw, &h->b_z,
                  &h->b_omega, &h->b_Ac, &h->b_B, &h->b_Z, &h->b_Xc, &h->b_Qc, &h->b_X0c,
                  &h->b_Q1, &h->b_Q2, &h->b_AQ, &h->b_AX, &h->b_G, &h->b_part, &h->b_Rinv,
@@ -603,6 +623,7 @@ int feast_destroy(feast_handle h) {
                  &h->b_rank, &h->b_W, &h->b_flag, &h->b_diag, &h->b_pow, &h->b_mu,
                  &h->b_Reig, &h->b_Y64, &h->b_AY, &h->b_rho};
   for (Buf* b : bufs) b->release();
+  if (h->own_stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return 0;
 }
@@ -629,6 +650,7 @@ void feast_invalidate(feast_handle h) {
   if (!h) return;
   h->f_valid = false;
   h->ac_valid = false;
+  for (feast_ctx* w : h->workers) feast_invalidate(w);
 }
 
 int feast_filter_apply(feast_handle h, feast_dtype dt, int n, const void* A, int lda,
@@ -887,6 +909,65 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
   }
 }
 
+int feast_solve_batched(feast_handle h, feast_dtype dt, int nprob, const feast_problem* probs,
+                        const feast_opts* opt, int nstreams) {
+  if (!h) return -1;
+  if (dt != FEAST_R64 && dt != FEAST_C128) return -2;
+  if (nprob < 0) return -3;
+  if (nprob > 0 && !probs) return -4;
+  if (!opt) return -5;
+  if (nstreams < 1 || nstreams > 32) return -6;
+  if (nprob == 0) return 0;
+  try {
+    FEAST_HIP(hipSetDevice(h->device));
+    while ((int)h->workers.size() < nstreams) {
+      hipStream_t st;
+      FEAST_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      feast_handle w = nullptr;
+      int rc = feast_create(&w, st);
+      if (rc) {
+        (void)hipStreamDestroy(st);
+        return rc;
+      }
+      w->prof.on = h->prof.on;
+      h->workers.push_back(w);
+      h->worker_streams.push_back(st);
+    }
+    std::vector<int> order(nprob);
+    for (int i = 0; i < nprob; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return (double)probs[a].n * probs[a].n * probs[a].n >
+             (double)probs[b].n * probs[b].n * probs[b].n;
+    });
+    std::atomic<int> next(0);
+    const int dev = h->device;
+    auto work = [&](int wi) {
+      (void)hipSetDevice(dev);
+      feast_ctx* wh = h->workers[wi];
+      for (int k = next.fetch_add(1); k < nprob; k = next.fetch_add(1)) {
+        const feast_problem& p = probs[order[k]];
+        feast_opts o = *opt;
+        o.m0 = p.m0;
+        o.anorm = p.anorm;
+        int st = -7;
+        if (p.lambda && p.res && p.m && p.iters)
+          st = feast_solve(wh, dt, p.n, p.A, p.lda, p.emin, p.emax, &o, p.X0, p.X, p.ldx,
+                           p.lambda, p.res, p.m, p.iters, nullptr);
+        if (p.status) *p.status = st;
+      }
+    };
+    std::vector<std::thread> threads;
+    for (int wi = 0; wi < nstreams; ++wi) threads.emplace_back(work, wi);
+    for (auto& t : threads) t.join();
+    int bad = 0;
+    for (int i = 0; i < nprob; ++i)
+      if (!probs[i].status || *probs[i].status != FEAST_OK) bad++;
+    return bad;
+  } catch (const HipError& e) {
+    return fail_hip(h, e);
+  }
+}
+
 int feast_get_filter_values(feast_handle h, double* mu, int m0) {
   if (!h || !mu) return 0;
   int k = std::min(m0, (int)h->mu.size());
@@ -903,6 +984,7 @@ int feast_get_timings(feast_handle h, double* out, int count) {
 
 int feast_set_profiling(feast_handle h, int on) {
   if (!h) return -1;
+  for (feast_ctx* w : h->workers) feast_set_profiling(w, on);
   h->prof.on = (on != 0);
   for (int c = 0; c < NCLASS; ++c) {
     h->prof.ms[c] = 0;
@@ -916,9 +998,16 @@ int feast_get_kernel_stats(feast_handle h, int kclass, double* total_ms, long lo
                            double* dense_flops) {
   if (!h) return -1;
   if (kclass < 0 || kclass >= NCLASS) return -2;
-  if (total_ms) *total_ms = h->prof.ms[kclass];
-  if (launches) *launches = h->prof.launches[kclass];
-  if (dense_flops) *dense_flops = h->prof.flops[kclass];
+  double ms = h->prof.ms[kclass], fl = h->prof.flops[kclass];
+  long long nl = h->prof.launches[kclass];
+  for (feast_ctx* w : h->workers) {
+    ms += w->prof.ms[kclass];
+    fl += w->prof.flops[kclass];
+    nl += w->prof.launches[kclass];
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = nl;
+  if (dense_flops) *dense_flops = fl;
   return 0;
 }
 

@@ -113,8 +113,20 @@ void upper_inverse(hipStream_t s, const zd* R, int m, int ldr, zd* Rinv, int ldi
 // Cyclic parallel-order Jacobi on the Hermitian m x m matrix H (ld = m, destroyed).
 // Returns sweeps used (host sync per sweep) or -1.  d (device, m) eigenvalues unsorted,
 // V (device, m x m) eigenvectors.
+// One sweep is recorded as a HIP graph (rounds, then a fill kernel and the check: no memset
+// node) and replayed per sweep when cache is given; the graph is re-recorded when the sizes
+// or buffers change.
+struct JacobiGraph {
+  void* graph = nullptr;
+  void* exec = nullptr;
+  int mp = 0;
+  const void* A0 = nullptr;
+  const void* V = nullptr;
+  const void* flag = nullptr;
+  ~JacobiGraph();
+};
 int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* dflag,
-                int max_sweeps);
+                int max_sweeps, JacobiGraph* cache = nullptr);
 // Stable ascending sort of d; Wout = V[:, order] (first m columns), lam = d[order].
 void sort_eigen(hipStream_t s, const double* d, const zd* V, int m, int mp, double* lam, zd* W,
                 int* rank);

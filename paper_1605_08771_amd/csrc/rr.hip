@@ -451,8 +451,42 @@ void upper_inverse(hipStream_t s, const zd* R, int m, int ldr, zd* Rinv, int ldi
   }
 }
 
+__global__ void zero_int_kernel(int* p) { p[0] = 0; }
+__global__ void copy_pair_kernel(const zd* __restrict__ a, zd* __restrict__ b, const zd* __restrict__ c,
+                                 zd* __restrict__ d, long count) {
+  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx < count) {
+    b[idx] = a[idx];
+    d[idx] = c[idx];
+  }
+}
+
+// One sweep (mp - 1 rounds, ending on the buffers it started from) followed by the
+// convergence check, either launched directly or recorded into a graph by stream capture.
+static void jacobi_sweep_launches(hipStream_t s, zd* A0, zd* A1, zd* V0, zd* V1, int mp, int* dflag) {
+  const long nthreads = (long)(mp / 2) * (mp / 2) + (long)mp * (mp / 2);
+  zd *Ain = A0, *Aout = A1, *Vin = V0, *Vout = V1;
+  for (int r = 0; r < mp - 1; ++r) {
+    hipLaunchKernelGGL(jacobi_round_kernel, grid1(nthreads), dim3(256), 0, s, Ain, Aout, Vin, Vout,
+                       mp, r);
+    std::swap(Ain, Aout);
+    std::swap(Vin, Vout);
+  }
+  if (Ain != A0) {  // odd round count: bring the result back to the starting buffers
+    hipLaunchKernelGGL(copy_pair_kernel, grid1((long)mp * mp), dim3(256), 0, s, Ain, A0, Vin, V0,
+                       (long)mp * mp);
+  }
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, dflag);
+  hipLaunchKernelGGL(jacobi_check_kernel, grid1((long)mp * mp), dim3(256), 0, s, A0, mp, dflag);
+}
+
+JacobiGraph::~JacobiGraph() {
+  if (exec) (void)hipGraphExecDestroy((hipGraphExec_t)exec);
+  if (graph) (void)hipGraphDestroy((hipGraph_t)graph);
+}
+
 int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* dflag,
-                int max_sweeps) {
+                int max_sweeps, JacobiGraph* cache) {
   // work: 3 * mp * mp complex (A ping, A pong, V pong); V is mp x mp.
   const int mp = m + (m & 1);
   zd* A0 = work;
@@ -465,30 +499,40 @@ int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* df
     FEAST_LAUNCH_CHECK();
     return 0;
   }
-  const long nthreads = (long)(mp / 2) * (mp / 2) + (long)mp * (mp / 2);
-  zd *Ain = A0, *Aout = A1, *Vin = V, *Vout = V1;
+  hipGraphExec_t exec = nullptr;
+  if (cache && s) {  // the legacy null stream cannot be captured
+    if (!(cache->exec && cache->mp == mp && cache->A0 == A0 && cache->V == V &&
+          cache->flag == dflag)) {
+      if (cache->exec) FEAST_HIP(hipGraphExecDestroy((hipGraphExec_t)cache->exec));
+      if (cache->graph) FEAST_HIP(hipGraphDestroy((hipGraph_t)cache->graph));
+      cache->exec = cache->graph = nullptr;
+      hipGraph_t g = nullptr;
+      FEAST_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      jacobi_sweep_launches(s, A0, A1, V, V1, mp, dflag);
+      FEAST_HIP(hipStreamEndCapture(s, &g));
+      hipGraphExec_t ge = nullptr;
+      FEAST_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+      cache->graph = g;
+      cache->exec = ge;
+      cache->mp = mp;
+      cache->A0 = A0;
+      cache->V = V;
+      cache->flag = dflag;
+    }
+    exec = (hipGraphExec_t)cache->exec;
+  }
   int sweeps = 0;
   bool converged = false;
   for (; sweeps < max_sweeps && !converged; ++sweeps) {
-    for (int r = 0; r < mp - 1; ++r) {
-      hipLaunchKernelGGL(jacobi_round_kernel, grid1(nthreads), dim3(256), 0, s, Ain, Aout, Vin,
-                         Vout, mp, r);
-      FEAST_LAUNCH_CHECK();
-      std::swap(Ain, Aout);
-      std::swap(Vin, Vout);
-    }
-    FEAST_HIP(hipMemsetAsync(dflag, 0, sizeof(int), s));
-    hipLaunchKernelGGL(jacobi_check_kernel, grid1((long)mp * mp), dim3(256), 0, s, Ain, mp, dflag);
+    if (exec) FEAST_HIP(hipGraphLaunch(exec, s));
+    else jacobi_sweep_launches(s, A0, A1, V, V1, mp, dflag);
     FEAST_LAUNCH_CHECK();
     int h = 0;
     FEAST_HIP(hipMemcpyAsync(&h, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
     FEAST_HIP(hipStreamSynchronize(s));
     converged = (h == 0);
   }
-  if (Vin != V) {
-    FEAST_HIP(hipMemcpyAsync(V, Vin, sizeof(zd) * (size_t)mp * mp, hipMemcpyDeviceToDevice, s));
-  }
-  hipLaunchKernelGGL(diag_kernel, grid1(mp), dim3(256), 0, s, Ain, mp, d);
+  hipLaunchKernelGGL(diag_kernel, grid1(mp), dim3(256), 0, s, A0, mp, d);
   FEAST_LAUNCH_CHECK();
   return converged ? sweeps : -1;
 }

@@ -158,3 +158,18 @@ def test_binding_rejects_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(fm, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         fm.lib()
+
+
+def test_batched_argument_checks():
+    L = fm.lib()
+    o = fm.FeastOpts(n_c=8, m0=4, max_iter=10, refine_max=0, tol=1e-12, anorm=1.0, prec=0, seed=1)
+    arr = (fm.FeastProblem * 1)()
+    f = L.feast_solve_batched
+    assert f(None, 1, 1, arr, ctypes.byref(o), 4) == -1
+    assert f(BAD, 5, 1, arr, ctypes.byref(o), 4) == -2
+    assert f(BAD, 1, -1, arr, ctypes.byref(o), 4) == -3
+    assert f(BAD, 1, 1, None, ctypes.byref(o), 4) == -4
+    assert f(BAD, 1, 1, arr, None, 4) == -5
+    assert f(BAD, 1, 1, arr, ctypes.byref(o), 0) == -6
+    assert f(BAD, 1, 1, arr, ctypes.byref(o), 33) == -6
+    assert f(BAD, 1, 0, arr, ctypes.byref(o), 4) == 0
