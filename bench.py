@@ -136,13 +136,13 @@ def bench_batched(args, dev):
         results.append(one(args.nstreams))
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
+    solve = f.kernel_stats("solve")
     f.set_profiling(False)
     bad, outs = results[-1]
     ok, err = check(outs)
     iters = [o["iters"] for o in outs]
     log(f"[bench] c4: bad={bad} ok={ok} max|dlam|={err:.2e} iters min/med/max "
         f"{min(iters)}/{int(np.median(iters))}/{max(iters)} time/step {total / args.steps:.3f}s")
-    solve = f.kernel_stats("solve")
     alg = sum(o["iters"] * 8 * 2 * 8.0 * p.n * p.n * p.m0 for p, o in zip(probs, outs)) * args.steps
     peak = PEAK_FP64_MFMA if prec == fm.FEAST_FP64 else PEAK_FP32_MFMA
     torch.cuda.synchronize()

@@ -56,6 +56,8 @@ def lib():
                                      ctypes.c_double, _dp, ctypes.c_int, _dp, ctypes.c_int,
                                      _dp, _dp, _ip, _ip, _dp]
         L.or_feast_solve_ex.argtypes = L.or_feast_solve.argtypes + [ctypes.c_int, _dp]
+        L.or_xrfeast_solve.argtypes = [ctypes.c_int] + L.or_feast_solve.argtypes[:7] + [
+            ctypes.c_int, ctypes.c_int] + L.or_feast_solve.argtypes[8:] + [ctypes.c_int, _dp]
         L.or_num_threads.restype = ctypes.c_int
         L.or_set_num_threads.argtypes = [ctypes.c_int]
         L.or_set_fault.argtypes = [ctypes.c_int]
@@ -180,3 +182,25 @@ def feast_solve(dtype, A, emin, emax, nc, m0, tol, max_iter, anorm, X0, spurious
     if spurious:
         out["mu"] = mu
     return out
+
+
+def xrfeast_solve(variant, dtype, A, emin, emax, nc, m0, s, tol, max_iter, anorm, X0,
+                  spurious=False):
+    """variant "x" = XFEAST, "r" = RFEAST (Sec. 2, Appendix boxes); s = blocks in the window
+    (XFEAST) or Rayleigh-Ritz steps per filter application (RFEAST)."""
+    A = _fort(A, dtype)
+    X0 = _fort(X0, dtype)
+    n = A.shape[0]
+    X = np.zeros((n, m0), dtype=A.dtype, order="F")
+    lam = np.zeros(m0)
+    res = np.zeros(m0)
+    m = ctypes.c_int(0)
+    iters = ctypes.c_int(0)
+    trace = np.zeros(max_iter)
+    mu = np.zeros(m0)
+    st = lib().or_xrfeast_solve({"x": 1, "r": 2}[variant], _dt(dtype), n, _ptr(A), n, emin,
+                                emax, nc, m0, s, tol, max_iter, anorm, _ptr(X0), n, _ptr(X), n,
+                                _ptr(lam), _ptr(res), ctypes.byref(m), ctypes.byref(iters),
+                                _ptr(trace), int(spurious), _ptr(mu))
+    return dict(status=st, X=X, lam=lam, res=res, m=m.value, iters=iters.value,
+                trace=trace[: iters.value], mu=mu)

@@ -636,3 +636,247 @@ int or_feast_solve(int dtype, int n, const double* A, int lda, double emin, doub
   return or_feast_solve_ex(dtype, n, A, lda, emin, emax, nc, m0, tol, max_iter, anorm, X0, ldx0,
                            X, ldx, lambda, res, m, iters, trace, 0, NULL);
 }
+
+
+/* =======================================================================================
+ * Expanded-subspace variants of Sec. 2 (Appendix, XFEAST and RFEAST algorithms).
+ * ===================================================================================== */
+
+/* Orthonormal basis of span(B) (n x k) by the Gram route of Sec. 2 (Method 1):
+ * B^H B = V S^2 V^H (Jacobi), U = B V S^{-1}, keeping the directions with
+ * s^2 > 1e-14 s^2_max (the numerically independent part).  Returns the rank r; U is n x r. */
+static int gram_orthonormal(int n, int k, const zc* B, zc* U) {
+  zc* G = malloc(sizeof(zc) * (size_t)k * k);
+  zc* V = malloc(sizeof(zc) * (size_t)k * k);
+  double* s2 = malloc(sizeof(double) * k);
+  matmul(1, k, k, n, B, n, B, n, G);
+  hermitize(k, G);
+  jacobi(k, G, k, s2, V, k);
+  double smax = 0.0;
+  for (int j = 0; j < k; j++) if (s2[j] > smax) smax = s2[j];
+  int r = 0;
+  for (int j = 0; j < k; j++) {
+    if (!(s2[j] > 1e-14 * smax)) continue;
+    double sinv = 1.0 / sqrt(s2[j]);
+    for (int i = 0; i < n; i++) {
+      zc acc = 0.0;
+      for (int l = 0; l < k; l++) acc += B[i + (size_t)l * n] * V[l + (size_t)j * k];
+      U[i + (size_t)r * n] = acc * sinv;
+    }
+    r++;
+  }
+  free(G); free(V); free(s2);
+  return r;
+}
+
+/* Rayleigh-Ritz on an orthonormal U (n x r): all r Ritz pairs, ascending, with residuals
+ * ||A y - lambda y|| / anorm (Appendix, step 2.i on an orthonormal basis). */
+static void rr_all(int n, const zc* A, const zc* U, int r, double anorm, zc* Y, double* lam,
+                   double* res) {
+  zc* AU = malloc(sizeof(zc) * (size_t)n * r);
+  zc* H = malloc(sizeof(zc) * (size_t)r * r);
+  zc* Z = malloc(sizeof(zc) * (size_t)r * r);
+  double* d = malloc(sizeof(double) * r);
+  int* order = malloc(sizeof(int) * r);
+  matmul(0, n, r, n, A, n, U, n, AU);
+  matmul(1, r, r, n, U, n, AU, n, H);
+  hermitize(r, H);
+  jacobi(r, H, r, d, Z, r);
+  for (int k = 0; k < r; k++) order[k] = k;
+  for (int k = 1; k < r; k++) {
+    int v = order[k], i = k - 1;
+    while (i >= 0 && d[order[i]] > d[v]) { order[i + 1] = order[i]; i--; }
+    order[i + 1] = v;
+  }
+  for (int k = 0; k < r; k++) {
+    int src = order[k];
+    lam[k] = d[src];
+    double rr = 0.0;
+    for (int i = 0; i < n; i++) {
+      zc y = 0.0, ay = 0.0;
+      for (int l = 0; l < r; l++) {
+        y += U[i + (size_t)l * n] * Z[l + (size_t)src * r];
+        ay += AU[i + (size_t)l * n] * Z[l + (size_t)src * r];
+      }
+      Y[i + (size_t)k * n] = y;
+      zc e = ay - lam[k] * y;
+      rr += creal(e) * creal(e) + cimag(e) * cimag(e);
+    }
+    res[k] = sqrt(rr) / anorm;
+  }
+  free(AU); free(H); free(Z); free(d); free(order);
+}
+
+/* Selection of Sec. 2 (Method 1, also used by Method 2): every pair inside I, and if fewer
+ * than m0 are inside, the pairs outside with the lowest residuals.  Reading for the case the
+ * paper leaves open: with more than m0 inside, the m0 inside pairs with the lowest residuals.
+ * Writes sel[0..m0) (indices into the r pairs, ascending by lambda) and returns the count
+ * selected (min(m0, r)). */
+static int select_pairs(int r, const double* lam, const double* res, double emin, double emax,
+                        int m0, int* sel) {
+  int* idx = malloc(sizeof(int) * r);
+  int cnt = 0;
+  /* inside, by residual */
+  for (int k = 0; k < r; k++) if (lam[k] > emin && lam[k] < emax) idx[cnt++] = k;
+  int nin = cnt;
+  for (int a = 1; a < nin; a++) {
+    int v = idx[a], b = a - 1;
+    while (b >= 0 && res[idx[b]] > res[v]) { idx[b + 1] = idx[b]; b--; }
+    idx[b + 1] = v;
+  }
+  for (int k = 0; k < r; k++) if (!(lam[k] > emin && lam[k] < emax)) idx[cnt++] = k;
+  for (int a = nin + 1; a < r; a++) {
+    int v = idx[a], b = a - 1;
+    while (b >= nin && res[idx[b]] > res[v]) { idx[b + 1] = idx[b]; b--; }
+    idx[b + 1] = v;
+  }
+  int take = r < m0 ? r : m0;
+  for (int a = 0; a < take; a++) sel[a] = idx[a];
+  /* ascending by lambda */
+  for (int a = 1; a < take; a++) {
+    int v = sel[a], b = a - 1;
+    while (b >= 0 && lam[sel[b]] > lam[v]) { sel[b + 1] = sel[b]; b--; }
+    sel[b + 1] = v;
+  }
+  free(idx);
+  return take;
+}
+
+/* XFEAST (Appendix): X' = [X_0, rho X_0, ..., rho^{s-1} X_0]; repeat: orthogonalize X'
+ * (Gram route), Rayleigh-Ritz on span X', select m0 pairs, stop if their largest residual
+ * inside I is <= tol, else filter the selected block and slide the window of s blocks.
+ * variant = 1 (XFEAST) or 2 (RFEAST: X' = rho X_i, then s Rayleigh-Ritz steps each
+ * expanding X' by the residual block R = A X - X Lambda of the selected pairs; the number of
+ * pairs inside I at the first step, m_e, fixes how many inside pairs (lowest residuals)
+ * count in step 3).  spurious = 1 additionally requires mu_k = Re(x^H rho(A) x) > 1/2 for a
+ * counted pair (as in or_feast_solve_ex).  trace[it-1] = r of outer iteration it. */
+int or_xrfeast_solve(int variant, int dtype, int n, const double* A, int lda, double emin,
+                     double emax, int nc, int m0, int s, double tol, int max_iter, double anorm,
+                     const double* X0, int ldx0, double* X, int ldx, double* lambda, double* res,
+                     int* m, int* iters, double* trace, int spurious, double* mu_out) {
+  if (variant != 1 && variant != 2) return -1;
+  if (dtype != 0 && dtype != 1) return -2;
+  if (n < 1) return -3;
+  if (!A || lda < n) return -4;
+  if (!(emin < emax)) return -6;
+  if (nc < 1) return -8;
+  if (m0 < 1 || m0 > n) return -9;
+  if (s < 1 || s * m0 > n) return -10;
+  if (!(tol > 0.0) || max_iter < 1 || !(anorm > 0.0)) return -11;
+  if (!X0 || ldx0 < n || !X || ldx < n || !lambda || !res || !m || !iters) return -15;
+  zc* Az = load_matrix(dtype, n, n, A, lda);
+  if (!all_finite(Az, (size_t)n * n)) { free(Az); return 5; }
+  const int K = s * m0 + m0; /* room for the RFEAST expansion */
+  zc* Xs = load_matrix(dtype, n, m0, X0, ldx0);
+  zc* Bw = malloc(sizeof(zc) * (size_t)n * K);  /* X' (window or expanded basis) */
+  zc* U = malloc(sizeof(zc) * (size_t)n * K);
+  zc* Y = malloc(sizeof(zc) * (size_t)n * K);
+  zc* Fq = malloc(sizeof(zc) * (size_t)n * m0);
+  double* lam = malloc(sizeof(double) * K);
+  double* rs = malloc(sizeof(double) * K);
+  int* sel = malloc(sizeof(int) * m0);
+  double* mu = malloc(sizeof(double) * m0);
+  factors_t f;
+  memset(&f, 0, sizeof(f));
+  int st = factors_build(&f, Az, n, emin, emax, nc);
+  int it = 0, prev_m = -1, mm = 0, kcols = 0;
+  if (st == 0 && variant == 1) { /* step 0: the Krylov-like window of filtered blocks */
+    memcpy(Bw, Xs, sizeof(zc) * (size_t)n * m0);
+    for (int b = 1; b < s; b++)
+      filter_with_factors(&f, dtype, Bw + (size_t)(b - 1) * n * m0, m0, Bw + (size_t)b * n * m0);
+    kcols = s * m0;
+  }
+  if (st == 0) {
+    st = 1;
+    for (it = 1; it <= max_iter; it++) {
+      int take = 0, me = -1;
+      if (variant == 1) {
+        int r = gram_orthonormal(n, kcols, Bw, U);
+        if (r < 1) { st = 4; break; }
+        rr_all(n, Az, U, r, anorm, Y, lam, rs);
+        take = select_pairs(r, lam, rs, emin, emax, m0, sel);
+      } else {
+        filter_with_factors(&f, dtype, Xs, m0, Bw); /* step 1 */
+        kcols = m0;
+        for (int j = 1; j <= s; j++) { /* step 2 */
+          int r = gram_orthonormal(n, kcols, Bw, U);
+          if (r < 1) { st = 4; break; }
+          rr_all(n, Az, U, r, anorm, Y, lam, rs);
+          take = select_pairs(r, lam, rs, emin, emax, m0, sel);
+          if (j == 1) {
+            me = 0;
+            for (int a = 0; a < r; a++) if (lam[a] > emin && lam[a] < emax) me++;
+          }
+          if (j < s) { /* R = A X - X Lambda appended to X' */
+            for (int a = 0; a < take; a++) {
+              const zc* y = Y + (size_t)sel[a] * n;
+              zc* rcol = Bw + (size_t)(kcols + a) * n;
+              for (int i = 0; i < n; i++) {
+                zc acc = 0.0;
+                for (int l = 0; l < n; l++) acc += Az[i + (size_t)l * n] * y[l];
+                rcol[i] = acc - lam[sel[a]] * y[i];
+              }
+            }
+            kcols += take;
+          }
+        }
+        if (st == 4) break;
+      }
+      /* the m0 selected pairs become X_{i+1} */
+      double lam_sel[m0 > 0 ? m0 : 1], res_sel[m0 > 0 ? m0 : 1];
+      for (int a = 0; a < take; a++) {
+        memcpy(Xs + (size_t)a * n, Y + (size_t)sel[a] * n, sizeof(zc) * n);
+        lam_sel[a] = lam[sel[a]];
+        res_sel[a] = rs[sel[a]];
+      }
+      for (int a = take; a < m0; a++) { lam_sel[a] = INFINITY; res_sel[a] = INFINITY; }
+      for (int a = 0; a < m0; a++) { lambda[a] = lam_sel[a]; res[a] = res_sel[a]; }
+      filter_with_factors(&f, dtype, Xs, m0, Fq); /* rho(A) X_{i+1}: next window block / mu */
+      for (int a = 0; a < take; a++) {
+        double d = 0.0;
+        for (int i = 0; i < n; i++) d += creal(conj(Xs[i + (size_t)a * n]) * Fq[i + (size_t)a * n]);
+        mu[a] = d;
+      }
+      /* step 3 */
+      int cand[m0 > 0 ? m0 : 1], nc_in = 0;
+      for (int a = 0; a < take; a++) {
+        if (!(lambda[a] > emin && lambda[a] < emax)) continue;
+        if (spurious && !(mu[a] > 0.5)) continue;
+        cand[nc_in++] = a;
+      }
+      if (variant == 2 && !spurious && me >= 0 && nc_in > me) { /* keep the me lowest residuals */
+        for (int a = 1; a < nc_in; a++) {
+          int v = cand[a], b = a - 1;
+          while (b >= 0 && res[cand[b]] > res[v]) { cand[b + 1] = cand[b]; b--; }
+          cand[b + 1] = v;
+        }
+        nc_in = me;
+      }
+      double r = 0.0;
+      for (int a = 0; a < nc_in; a++) if (res[cand[a]] > r) r = res[cand[a]];
+      mm = nc_in;
+      *m = mm;
+      if (trace) trace[it - 1] = r;
+      if (mm == 0) {
+        if (prev_m == 0) { st = 3; break; }
+      } else if (mm >= m0 && it >= 2) {
+        st = 2; break;
+      } else if (r <= tol) {
+        st = 0; break;
+      }
+      prev_m = mm;
+      if (variant == 1) { /* step 4: slide the window */
+        memmove(Bw, Bw + (size_t)n * m0, sizeof(zc) * (size_t)n * m0 * (s - 1));
+        memcpy(Bw + (size_t)(s - 1) * n * m0, Fq, sizeof(zc) * (size_t)n * m0);
+      }
+    }
+    if (it > max_iter) it = max_iter;
+  }
+  if (mu_out) for (int a = 0; a < m0; a++) mu_out[a] = mu[a];
+  *iters = it;
+  store_matrix(dtype, n, m0, Xs, X, ldx);
+  factors_free(&f);
+  free(Az); free(Xs); free(Bw); free(U); free(Y); free(Fq); free(lam); free(rs); free(sel);
+  free(mu);
+  return st;
+}

@@ -42,6 +42,10 @@ int or_feast_solve_ex(int dtype, int n, const double* A, int lda, double emin, d
                       int nc, int m0, double tol, int max_iter, double anorm, const double* X0,
                       int ldx0, double* X, int ldx, double* lambda, double* res, int* m,
                       int* iters, double* trace, int spurious, double* mu_out);
+int or_xrfeast_solve(int variant, int dtype, int n, const double* A, int lda, double emin,
+                     double emax, int nc, int m0, int s, double tol, int max_iter, double anorm,
+                     const double* X0, int ldx0, double* X, int ldx, double* lambda, double* res,
+                     int* m, int* iters, double* trace, int spurious, double* mu_out);
 int or_num_threads(void);
 void or_set_num_threads(int n);
 void or_set_fault(int code);
