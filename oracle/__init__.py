@@ -58,6 +58,8 @@ def lib():
         L.or_feast_solve_ex.argtypes = L.or_feast_solve.argtypes + [ctypes.c_int, _dp]
         L.or_xrfeast_solve.argtypes = [ctypes.c_int] + L.or_feast_solve.argtypes[:7] + [
             ctypes.c_int, ctypes.c_int] + L.or_feast_solve.argtypes[8:] + [ctypes.c_int, _dp]
+        L.or_select_pairs.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int, _ip]
         L.or_num_threads.restype = ctypes.c_int
         L.or_set_num_threads.argtypes = [ctypes.c_int]
         L.or_set_fault.argtypes = [ctypes.c_int]
@@ -182,6 +184,16 @@ def feast_solve(dtype, A, emin, emax, nc, m0, tol, max_iter, anorm, X0, spurious
     if spurious:
         out["mu"] = mu
     return out
+
+
+def select_pairs(lam, res, emin, emax, m0):
+    """Indices of the m0 pairs the expanded-subspace methods keep (Sec. 2, Method 1)."""
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    res = np.ascontiguousarray(res, dtype=np.float64)
+    sel = np.zeros(max(m0, 1), dtype=np.int32)
+    k = lib().or_select_pairs(len(lam), _ptr(lam), _ptr(res), emin, emax, m0,
+                              sel.ctypes.data_as(_ip))
+    return sel[:k]
 
 
 def xrfeast_solve(variant, dtype, A, emin, emax, nc, m0, s, tol, max_iter, anorm, X0,

@@ -642,14 +642,28 @@ int or_feast_solve(int dtype, int n, const double* A, int lda, double emin, doub
  * Expanded-subspace variants of Sec. 2 (Appendix, XFEAST and RFEAST algorithms).
  * ===================================================================================== */
 
-/* Orthonormal basis of span(B) (n x k) by the Gram route of Sec. 2 (Method 1):
+/* Orthonormal basis of span(B) (n x k) by the Gram route of Sec. 2 (Method 1), applied to B
+ * with its columns first scaled to unit length (a diagonal scaling leaves the span, and so the
+ * Rayleigh-Ritz pairs, unchanged; without it the residual columns of RFEAST, orders of
+ * magnitude shorter than the filtered ones, would sit below any rank threshold):
  * B^H B = V S^2 V^H (Jacobi), U = B V S^{-1}, keeping the directions with
  * s^2 > 1e-14 s^2_max (the numerically independent part).  Returns the rank r; U is n x r. */
 static int gram_orthonormal(int n, int k, const zc* B, zc* U) {
+  zc* Bn = malloc(sizeof(zc) * (size_t)n * k);
   zc* G = malloc(sizeof(zc) * (size_t)k * k);
   zc* V = malloc(sizeof(zc) * (size_t)k * k);
   double* s2 = malloc(sizeof(double) * k);
-  matmul(1, k, k, n, B, n, B, n, G);
+  for (int j = 0; j < k; j++) {
+    double nrm = 0.0;
+    for (int i = 0; i < n; i++) {
+      zc v = B[i + (size_t)j * n];
+      nrm += creal(v) * creal(v) + cimag(v) * cimag(v);
+    }
+    nrm = sqrt(nrm);
+    double sc = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int i = 0; i < n; i++) Bn[i + (size_t)j * n] = B[i + (size_t)j * n] * sc;
+  }
+  matmul(1, k, k, n, Bn, n, Bn, n, G);
   hermitize(k, G);
   jacobi(k, G, k, s2, V, k);
   double smax = 0.0;
@@ -660,51 +674,23 @@ static int gram_orthonormal(int n, int k, const zc* B, zc* U) {
     double sinv = 1.0 / sqrt(s2[j]);
     for (int i = 0; i < n; i++) {
       zc acc = 0.0;
-      for (int l = 0; l < k; l++) acc += B[i + (size_t)l * n] * V[l + (size_t)j * k];
+      for (int l = 0; l < k; l++) acc += Bn[i + (size_t)l * n] * V[l + (size_t)j * k];
       U[i + (size_t)r * n] = acc * sinv;
     }
     r++;
   }
-  free(G); free(V); free(s2);
+  free(Bn); free(G); free(V); free(s2);
   return r;
 }
 
-/* Rayleigh-Ritz on an orthonormal U (n x r): all r Ritz pairs, ascending, with residuals
- * ||A y - lambda y|| / anorm (Appendix, step 2.i on an orthonormal basis). */
-static void rr_all(int n, const zc* A, const zc* U, int r, double anorm, zc* Y, double* lam,
-                   double* res) {
-  zc* AU = malloc(sizeof(zc) * (size_t)n * r);
-  zc* H = malloc(sizeof(zc) * (size_t)r * r);
-  zc* Z = malloc(sizeof(zc) * (size_t)r * r);
-  double* d = malloc(sizeof(double) * r);
-  int* order = malloc(sizeof(int) * r);
-  matmul(0, n, r, n, A, n, U, n, AU);
-  matmul(1, r, r, n, U, n, AU, n, H);
-  hermitize(r, H);
-  jacobi(r, H, r, d, Z, r);
-  for (int k = 0; k < r; k++) order[k] = k;
-  for (int k = 1; k < r; k++) {
-    int v = order[k], i = k - 1;
-    while (i >= 0 && d[order[i]] > d[v]) { order[i + 1] = order[i]; i--; }
-    order[i + 1] = v;
-  }
-  for (int k = 0; k < r; k++) {
-    int src = order[k];
-    lam[k] = d[src];
-    double rr = 0.0;
-    for (int i = 0; i < n; i++) {
-      zc y = 0.0, ay = 0.0;
-      for (int l = 0; l < r; l++) {
-        y += U[i + (size_t)l * n] * Z[l + (size_t)src * r];
-        ay += AU[i + (size_t)l * n] * Z[l + (size_t)src * r];
-      }
-      Y[i + (size_t)k * n] = y;
-      zc e = ay - lam[k] * y;
-      rr += creal(e) * creal(e) + cimag(e) * cimag(e);
-    }
-    res[k] = sqrt(rr) / anorm;
-  }
-  free(AU); free(H); free(Z); free(d); free(order);
+/* Rayleigh-Ritz on the orthogonalized basis U (n x r): step 2.i of the XFEAST and RFEAST
+ * algorithms, A' q = lambda B' q with A' = U^H A U and B' = U^H U (rr_core: unit Ritz vectors
+ * Y, ascending lambda, residuals ||A y - lambda y|| / anorm).  Returns rr_core's status. */
+static int rr_all(int n, const zc* A, const zc* U, int r, double anorm, zc* Y, double* lam,
+                  double* res) {
+  int mdummy = 0;
+  memcpy(Y, U, sizeof(zc) * (size_t)n * r);
+  return rr_core(n, A, Y, r, 0.0, 0.0, anorm, lam, res, &mdummy);
 }
 
 /* Selection of Sec. 2 (Method 1, also used by Method 2): every pair inside I, and if fewer
@@ -727,7 +713,11 @@ static int select_pairs(int r, const double* lam, const double* res, double emin
   for (int k = 0; k < r; k++) if (!(lam[k] > emin && lam[k] < emax)) idx[cnt++] = k;
   for (int a = nin + 1; a < r; a++) {
     int v = idx[a], b = a - 1;
-    while (b >= nin && res[idx[b]] > res[v]) { idx[b + 1] = idx[b]; b--; }
+    /* planted (6): highest residual first */
+    while (b >= nin && (g_fault == 6 ? res[idx[b]] < res[v] : res[idx[b]] > res[v])) {
+      idx[b + 1] = idx[b];
+      b--;
+    }
     idx[b + 1] = v;
   }
   int take = r < m0 ? r : m0;
@@ -740,6 +730,12 @@ static int select_pairs(int r, const double* lam, const double* res, double emin
   }
   free(idx);
   return take;
+}
+
+int or_select_pairs(int r, const double* lam, const double* res, double emin, double emax,
+                    int m0, int* sel) {
+  if (r < 0 || m0 < 1 || (r > 0 && (!lam || !res || !sel))) return -1;
+  return select_pairs(r, lam, res, emin, emax, m0, sel);
 }
 
 /* XFEAST (Appendix): X' = [X_0, rho X_0, ..., rho^{s-1} X_0]; repeat: orthogonalize X'
@@ -793,15 +789,21 @@ int or_xrfeast_solve(int variant, int dtype, int n, const double* A, int lda, do
       if (variant == 1) {
         int r = gram_orthonormal(n, kcols, Bw, U);
         if (r < 1) { st = 4; break; }
-        rr_all(n, Az, U, r, anorm, Y, lam, rs);
+        st = rr_all(n, Az, U, r, anorm, Y, lam, rs);
+        if (st) break;
+        st = 1;
         take = select_pairs(r, lam, rs, emin, emax, m0, sel);
       } else {
-        filter_with_factors(&f, dtype, Xs, m0, Bw); /* step 1 */
+        /* step 1: rho(A) X_i, already formed at the end of the previous iteration */
+        if (it == 1) filter_with_factors(&f, dtype, Xs, m0, Bw);
+        else memcpy(Bw, Fq, sizeof(zc) * (size_t)n * m0);
         kcols = m0;
         for (int j = 1; j <= s; j++) { /* step 2 */
           int r = gram_orthonormal(n, kcols, Bw, U);
           if (r < 1) { st = 4; break; }
-          rr_all(n, Az, U, r, anorm, Y, lam, rs);
+          st = rr_all(n, Az, U, r, anorm, Y, lam, rs);
+          if (st) break;
+          st = 1;
           take = select_pairs(r, lam, rs, emin, emax, m0, sel);
           if (j == 1) {
             me = 0;
@@ -817,10 +819,10 @@ int or_xrfeast_solve(int variant, int dtype, int n, const double* A, int lda, do
                 rcol[i] = acc - lam[sel[a]] * y[i];
               }
             }
-            kcols += take;
+            if (g_fault != 8) kcols += take; /* planted (8): basis never grows */
           }
         }
-        if (st == 4) break;
+        if (st != 1) break;
       }
       /* the m0 selected pairs become X_{i+1} */
       double lam_sel[m0 > 0 ? m0 : 1], res_sel[m0 > 0 ? m0 : 1];
@@ -865,7 +867,7 @@ int or_xrfeast_solve(int variant, int dtype, int n, const double* A, int lda, do
         st = 0; break;
       }
       prev_m = mm;
-      if (variant == 1) { /* step 4: slide the window */
+      if (variant == 1 && g_fault != 7) { /* step 4: slide the window (planted 7: not) */
         memmove(Bw, Bw + (size_t)n * m0, sizeof(zc) * (size_t)n * m0 * (s - 1));
         memcpy(Bw + (size_t)(s - 1) * n * m0, Fq, sizeof(zc) * (size_t)n * m0);
       }

@@ -46,6 +46,8 @@ int or_xrfeast_solve(int variant, int dtype, int n, const double* A, int lda, do
                      double emax, int nc, int m0, int s, double tol, int max_iter, double anorm,
                      const double* X0, int ldx0, double* X, int ldx, double* lambda, double* res,
                      int* m, int* iters, double* trace, int spurious, double* mu_out);
+int or_select_pairs(int r, const double* lam, const double* res, double emin, double emax,
+                    int m0, int* sel);
 int or_num_threads(void);
 void or_set_num_threads(int n);
 void or_set_fault(int code);

@@ -153,6 +153,23 @@ def make_problem(lam, emin, emax, m0, n_c, tol, max_iter, complex_, rng, device=
 # The five workloads.  Sizes can be scaled down (n=...) for tests; the recipe is unchanged.
 # --------------------------------------------------------------------------------------
 
+def fig2_problem(kind="dense", m0=51, n_c=None, complex_=False, tol=1e-12, max_iter=40,
+                 device=None, seed_tag=6, n=545, n_in=50):
+    """The two n=545 test matrices of Sec. 3 (the comparison of FEAST, XFEAST and RFEAST):
+    the same eigenvectors, n_in eigenvalues inside I=(-1, 1) and the other n - n_in uniform on
+    [1.01, 1.1] ("dense" outer spectrum) or [1.01, 20.81] ("sparse").  The paper does not say
+    how the inside eigenvalues are placed: here uniform on (-1, 1), at least DELTA from the
+    endpoints.  n_c defaults to the paper's choice for each matrix (8 dense, 3 sparse)."""
+    rng = rng_for([seed_tag, 0 if kind == "dense" else 1])
+    hi = {"dense": 1.1, "sparse": 20.81}[kind]
+    lam = np.concatenate([uniform_spectrum(rng, n_in, -1.0, 1.0, lo=-1.0, hi=1.0),
+                          rng.uniform(1.01, hi, size=n - n_in)])
+    if n_c is None:
+        n_c = 8 if kind == "dense" else 3
+    return make_problem(lam, -1.0, 1.0, m0, n_c, tol, max_iter, complex_, rng, device,
+                        name=f"fig2-{kind}")
+
+
 def config1(n=500, device=None, seed_tag=1):
     """Real symmetric, lam ~ U[-1,1], I = (-0.1, 0.1), m0 = 75, n_c = 8, tol 1e-12, 20 its."""
     rng = rng_for(seed_tag)
