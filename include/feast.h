@@ -53,6 +53,27 @@ typedef enum { FEAST_R64 = 0, FEAST_C128 = 1 } feast_dtype;
  * accuracy of the filtered block.  The Rayleigh-Ritz step is FP64 in both modes. */
 typedef enum { FEAST_FP64 = 0, FEAST_FP32_IR = 1 } feast_precision;
 
+/* The subspace iteration run by feast_solve.
+ * FEAST_METHOD_FEAST: the FEAST algorithm (Appendix).
+ * FEAST_METHOD_XFEAST: Sec. 2, Method 1 (Appendix, XFEAST algorithm): X' holds the last
+ *   `expand` filtered blocks, [X_0, rho X_0, ..., rho^{s-1} X_0] at the start; each iteration
+ *   orthogonalizes X', runs Rayleigh-Ritz on it, keeps m0 pairs (every pair inside I, then
+ *   the lowest residuals outside), and puts the filtered kept block in place of the oldest.
+ * FEAST_METHOD_RFEAST: Sec. 2, Method 2 (Appendix, RFEAST algorithm): X' = rho(A) X_i, then
+ *   `expand` Rayleigh-Ritz steps, each after the first on X' grown by the residual block
+ *   A X - X Lambda of the pairs kept by the previous step; unless opt->spurious is set, the
+ *   number of pairs inside I at the first step bounds how many pairs inside I (lowest
+ *   residuals) count in the convergence test.
+ * Both variants orthogonalize X' by its Gram matrix (X'^H X' = V S^2 V^H, U = X' V S^{-1}),
+ * with the columns of X' first scaled to unit length and directions with
+ * s^2 <= 1e-14 s^2_max dropped, then run Rayleigh-Ritz on U.  Both solve n_c * m0
+ * right-hand sides per iteration, like FEAST with the same m0. */
+typedef enum {
+  FEAST_METHOD_FEAST = 0,
+  FEAST_METHOD_XFEAST = 1,
+  FEAST_METHOD_RFEAST = 2
+} feast_method;
+
 typedef struct {
   int n_c;          /* quadrature nodes on the upper half circle (>= 1) */
   int m0;           /* subspace size, more than the number of eigenvalues in I */
@@ -74,6 +95,9 @@ typedef struct {
                        test: FP32 solves leave the strongly damped directions of the filtered
                        block at the FP32 noise floor, and Rayleigh-Ritz turns that noise into
                        Ritz pairs inside I with large residuals. */
+  int method;       /* feast_method; 0 = FEAST */
+  int expand;       /* XFEAST: blocks kept in X'; RFEAST: Rayleigh-Ritz steps per filter
+                       application; >= 1 with expand * m0 <= n (ignored by FEAST) */
 } feast_opts;
 
 #define FEAST_OK 0
@@ -127,17 +151,18 @@ int feast_rayleigh_ritz(feast_handle h, feast_dtype dt, int n, const void* A, in
                         int ldq, int m0, double emin, double emax, double anorm, double* lambda,
                         double* res, int* m);
 
-/* The FEAST algorithm (Appendix): X_0 = X0 (n x m0, leading dimension ldx; or a seeded
- * Gaussian block when X0 == NULL);
+/* The FEAST algorithm (Appendix), or the variant opt->method selects: X_0 = X0 (n x m0,
+ * leading dimension ldx; or a seeded Gaussian block when X0 == NULL);
  * repeat  Q = rho(A) X_i;  Rayleigh-Ritz on Q;  X_{i+1} = all m0 Ritz vectors  until the
- * largest residual of the Ritz pairs inside I is <= opt->tol.
+ * largest residual of the Ritz pairs inside I is <= opt->tol.  For XFEAST/RFEAST, lambda and
+ * res hold the m0 kept pairs (ascending lambda; +inf past the basis rank).
  *   X: n x m0 output (ldx >= n), may equal X0 only if ldx matches.
  *   lambda[m0], res[m0], *m, *iters: host outputs of the last iterate (*m counts the pairs
  *   inside I that pass the opt->spurious test).
  *   trace: NULL or host array of opt->max_iter doubles; trace[i-1] = largest in-interval
  *   residual after iteration i.
  * Argument positions: h=1 dt=2 n=3 A=4 lda=5 emin=6 emax=7 opt=8 (n_c, m0, max_iter, tol,
- * prec, refine_max checked) X0=9 X=10 ldx=11 lambda=12 res=13 m=14 iters=15.
+ * prec, refine_max, method, expand checked) X0=9 X=10 ldx=11 lambda=12 res=13 m=14 iters=15.
  * Returns FEAST_OK, FEAST_NOT_CONVERGED, FEAST_M0_TOO_SMALL, FEAST_NO_EIGENVALUES,
  * FEAST_B_NOT_SPD, FEAST_NONFINITE, FEAST_ZERO_PIVOT or an error. */
 int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, double emin,

@@ -26,11 +26,15 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "M0_TOO_SMALL", 3: "NO_EIGENVALUES",
 KCLASS = {"lu": 0, "solve": 1, "rr": 2, "refine": 3, "other": 4}
 
 
+METHODS = {"feast": 0, "xfeast": 1, "rfeast": 2}
+
+
 class FeastOpts(ctypes.Structure):
     _fields_ = [("n_c", ctypes.c_int), ("m0", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("refine_max", ctypes.c_int), ("tol", ctypes.c_double),
                 ("anorm", ctypes.c_double), ("prec", ctypes.c_int),
-                ("seed", ctypes.c_ulonglong), ("spurious", ctypes.c_int)]
+                ("seed", ctypes.c_ulonglong), ("spurious", ctypes.c_int),
+                ("method", ctypes.c_int), ("expand", ctypes.c_int)]
 
 
 class FeastProblem(ctypes.Structure):
@@ -189,7 +193,10 @@ class Feast:
         return st, lam, res, m.value
 
     def solve(self, A, emin, emax, m0, n_c=8, tol=1e-12, max_iter=50, anorm=0.0,
-              prec=FEAST_FP64, refine_max=4, X0=None, seed=0, X=None, spurious=False):
+              prec=FEAST_FP64, refine_max=4, X0=None, seed=0, X=None, spurious=False,
+              method="feast", expand=1):
+        """method: "feast", "xfeast" or "rfeast" (expand = blocks kept / Rayleigh-Ritz steps
+        per filter application)."""
         import numpy as np
         import torch
         dt = _dtype_code(A)
@@ -201,7 +208,8 @@ class Feast:
         if X0 is not None and _ld(X0, "X0") != ldx:
             raise ValueError("X0 and X must share the leading dimension")
         opts = FeastOpts(n_c=n_c, m0=m0, max_iter=max_iter, refine_max=refine_max, tol=tol,
-                         anorm=anorm, prec=prec, seed=seed, spurious=int(spurious))
+                         anorm=anorm, prec=prec, seed=seed, spurious=int(spurious),
+                         method=METHODS[method], expand=expand)
         lam = np.zeros(m0)
         res = np.zeros(m0)
         trace = np.zeros(max_iter)

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <thread>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -218,7 +219,10 @@ struct feast_ctx {
   std::vector<double> mu;
   PhaseTimer timer;
   KernelProfiler prof;
-  JacobiGraph jgraph;
+  std::map<int, JacobiGraph> jgraphs;  // recorded Jacobi sweeps, by padded order
+  // expanded-subspace variants
+  Buf b_win, b_U, b_Rsel, b_lsel, b_keep, b_sel, b_T;
+  std::vector<int> keep_h, sel_h;
   // batched workers (each with its own stream and workspace)
   std::vector<feast_ctx*> workers;
   std::vector<hipStream_t> worker_streams;
@@ -482,7 +486,7 @@ int cholqr_pass(feast_ctx* h, int n, int m0, const zd* Q1, zd* Q2, double shift_
 // Rayleigh-Ritz on Qin (n x m0 complex, ldq); Ritz vectors written back to Qin.
 int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m0, double emin,
             double emax, double anorm, double* lam_h, double* res_h, int* m_out,
-            zd* Reig = nullptr) {
+            zd* Reig = nullptr, bool quant = false) {
   hipStream_t s = h->stream;
   ScopedProf sp(h->prof, K_RR);
   hipEvent_t e0 = h->timer.mark(s);
@@ -545,12 +549,12 @@ int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m
     zgemm(s, OP_C, OP_N, m0, m0, n, zmake(1, 0), Q1, n, AQ, n, zmake(0, 0), part, m0, b);
     reduce_partials_hermitian(s, part, nsplit, m0, H, m0);
   }
-  const int mp = m0 + (m0 & 1);
+  const int mp = quant ? jacobi_order_quantized(m0) : jacobi_order(m0);
   double* d = h->b_d.get<double>(mp);
   zd* V = h->b_V.get<zd>((size_t)mp * mp);
   zd* jw = h->b_jac.get<zd>(3 * (size_t)mp * mp);
   int* dflag = h->b_flag.get<int>(64);
-  int sweeps = jacobi_eigh(s, H, m0, d, V, jw, dflag, 40, &h->jgraph);
+  int sweeps = jacobi_eigh(s, H, m0, d, V, jw, dflag, 40, &h->jgraphs[mp], mp);
   (void)sweeps;
   double* lam = h->b_lam.get<double>(mp);
   zd* W = h->b_W.get<zd>((size_t)m0 * m0);
@@ -582,6 +586,271 @@ void finish_timing(feast_ctx* h) {
   h->prof.flush();
 }
 
+
+// Set-up shared by the FEAST loop and its expanded-subspace variants: the complex operand
+// for Rayleigh-Ritz, ||A||_2 (given or estimated), the factors of the n_c shifted matrices
+// and the start block Xw (n x m0, from X0 or seeded Gaussian).  Returns 0 or a status.
+int solve_setup(feast_ctx* h, feast_dtype dt, int n, const void* A, int lda, double emin,
+                double emax, const feast_opts* opt, const void* X0, int ldx, const zd** Ac_out,
+                long* ldac, double* anorm_out, zd* Xw) {
+  hipStream_t s = h->stream;
+  const int m0 = opt->m0;
+  const zd* Ac = complex_A(h, dt, n, A, lda, ldac);
+  *Ac_out = Ac;
+  double anorm = opt->anorm;
+  if (!(anorm > 0)) {
+    zd* pw = h->b_pow.get<zd>(2 * (size_t)n);
+    double* dn = h->b_diag.get<double>(64);
+    anorm = norm2_estimate(s, Ac, *ldac, n, 30, pw, dn);
+    if (!(anorm > 0)) anorm = 1.0;
+  }
+  *anorm_out = anorm;
+  int st = ensure_factors(h, dt, n, A, lda, emin, emax, opt->n_c, opt->prec);
+  if (st) return st;
+  if (X0) {
+    if (dt == FEAST_R64) real_to_complex(s, (const double*)X0, ldx, Xw, n, n, m0);
+    else copy_matrix(s, (const zd*)X0, ldx, Xw, n, n, m0);
+  } else {
+    if (dt == FEAST_R64) {
+      double* tmp = (double*)h->b_Xc.get<zd>((size_t)n * m0);
+      gaussian_fill(s, tmp, n, n, m0, 1, opt->seed);
+      real_to_complex(s, tmp, n, Xw, n, n, m0);
+    } else {
+      gaussian_fill(s, Xw, n, n, m0, 0, opt->seed);
+    }
+  }
+  if (nonfinite_check(s, Xw, n, n, m0, h->b_flag.get<int>(64))) return FEAST_NONFINITE;
+  return 0;
+}
+
+// ---- Expanded-subspace variants (Sec. 2; Appendix, XFEAST and RFEAST algorithms) ---------
+
+// Orthonormal basis U (n x r, ld n) of span(B) (n x k, ld n) by the Gram route of Sec. 2
+// (Method 1), after scaling B's columns to unit length in place (a diagonal scaling keeps the
+// span; it keeps RFEAST's short residual columns above the rank threshold):
+// B^H B = V S^2 V^H (Jacobi), U = B V S^{-1} over the directions with s^2 > 1e-14 s^2_max.
+// Returns r (0: no direction left) or -1 if the Gram matrix is not finite.
+int gram_orthonormal(feast_ctx* h, int n, int k, zd* B, zd* U) {
+  hipStream_t s = h->stream;
+  normalize_columns(s, B, n, n, k);
+  const int nsplit = std::max(1, std::min(32, n / 256));
+  const int kc = (n + nsplit - 1) / nsplit;
+  zd* part = h->b_part.get<zd>((size_t)nsplit * k * k);
+  zd* G = h->b_G.get<zd>((size_t)k * k);
+  Batch b;
+  b.n1 = nsplit;
+  b.splitk = kc;
+  b.sC1 = (long)k * k;
+  zgemm(s, OP_C, OP_N, k, k, n, zmake(1, 0), B, n, B, n, zmake(0, 0), part, k, b);
+  reduce_partials_hermitian(s, part, nsplit, k, G, k);
+  const int mp = jacobi_order_quantized(k);
+  double* d = h->b_d.get<double>(mp);
+  zd* V = h->b_V.get<zd>((size_t)mp * mp);
+  zd* jw = h->b_jac.get<zd>(3 * (size_t)mp * mp);
+  int* dflag = h->b_flag.get<int>(64);
+  jacobi_eigh(s, G, k, d, V, jw, dflag, 40, &h->jgraphs[mp], mp);
+  std::vector<double> hd(k);
+  FEAST_HIP(hipMemcpyAsync(hd.data(), d, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  FEAST_HIP(hipStreamSynchronize(s));
+  double mx = 0;
+  for (double v : hd) {
+    if (!std::isfinite(v)) return -1;
+    mx = std::max(mx, v);
+  }
+  h->keep_h.clear();
+  for (int j = 0; j < k; ++j)
+    if (hd[j] > 1e-14 * mx) h->keep_h.push_back(j);
+  const int r = (int)h->keep_h.size();
+  if (r == 0) return 0;
+  int* dkeep = h->b_keep.get<int>(r);
+  FEAST_HIP(hipMemcpyAsync(dkeep, h->keep_h.data(), sizeof(int) * r, hipMemcpyHostToDevice, s));
+  zd* T = h->b_T.get<zd>((size_t)k * r);
+  gram_basis(s, d, V, mp, dkeep, k, r, T);
+  zgemm(s, OP_N, OP_N, n, r, k, zmake(1, 0), B, n, T, k, zmake(0, 0), U, n);
+  FEAST_HIP(hipStreamSynchronize(s));  // keep_h is reused by the next call
+  return r;
+}
+
+// Selection of Sec. 2 (Method 1; Method 2 uses the same): every pair inside I, then the pairs
+// outside by increasing residual, m0 in all; with more than m0 inside (left open by the
+// paper), the m0 inside pairs with the lowest residuals.  Ties keep the lower index.
+// sel = chosen indices in ascending lambda order; returns min(m0, r).
+int select_pairs(int r, const double* lam, const double* res, double emin, double emax, int m0,
+                 std::vector<int>& sel) {
+  std::vector<int> in, out;
+  for (int k = 0; k < r; ++k) (lam[k] > emin && lam[k] < emax ? in : out).push_back(k);
+  auto by_res = [&](int a, int b) { return res[a] < res[b]; };
+  std::stable_sort(in.begin(), in.end(), by_res);
+  std::stable_sort(out.begin(), out.end(), by_res);
+  sel.assign(in.begin(), in.end());
+  sel.insert(sel.end(), out.begin(), out.end());
+  const int take = std::min(m0, r);
+  sel.resize(take);
+  std::stable_sort(sel.begin(), sel.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+  return take;
+}
+
+// XFEAST (opt->method 1): X' = [X_0, rho X_0, ..., rho^{s-1} X_0]; each iteration
+// orthogonalizes X', runs Rayleigh-Ritz on it, keeps m0 pairs, tests them, filters the kept
+// block and puts it in place of the oldest block.  RFEAST (method 2): X' = rho(A) X_i, then s
+// Rayleigh-Ritz steps, each after the first on X' grown by the residual block R = A X - X Lambda
+// of the pairs kept by the previous one; m_e, the number of pairs inside I at the first step,
+// caps the pairs that count in the test (the lowest residuals among those inside I).
+// Xs holds X_0 on entry (n x m0, complex).  Outputs as feast_solve.
+int xr_solve(feast_ctx* h, feast_dtype dt, int n, const zd* Ac, long ldac, double anorm,
+             double emin, double emax, const feast_opts* opt, zd* Xs, void* X, int ldx,
+             double* lambda, double* res, int* m, int* iters, double* trace, hipEvent_t t0) {
+  hipStream_t s = h->stream;
+  const int m0 = opt->m0, sx = opt->expand, variant = opt->method;
+  const int K = sx * m0;
+  const bool mixed = opt->prec == FEAST_FP32_IR;
+  const bool spur = opt->spurious != 0 || mixed;
+  // Buffers sized once for the widest basis, so device pointers (and the recorded Jacobi
+  // sweeps that capture them) stay fixed while the basis width changes.
+  zd* W = h->b_win.get<zd>((size_t)n * K);
+  zd* U = h->b_U.get<zd>((size_t)n * K);
+  zd* Reig = h->b_Reig.get<zd>((size_t)n * K);
+  {
+    const int mq = jacobi_order_quantized(K);
+    h->b_d.get<double>(mq);
+    h->b_V.get<zd>((size_t)mq * mq);
+    h->b_jac.get<zd>(3 * (size_t)mq * mq);
+    h->b_flag.get<int>(64);
+  }
+  zd* Rsel = h->b_Rsel.get<zd>((size_t)n * m0);
+  double* lsel = h->b_lsel.get<double>(m0);
+  int* dsel = h->b_sel.get<int>(m0);
+  double* dmu = h->b_mu.get<double>(m0);
+  std::vector<double> lam_h(K), res_h(K);
+  h->mu.assign(m0, 0.0);
+  std::vector<int>& sel = h->sel_h;
+  auto upload_sel = [&](int take) {
+    FEAST_HIP(hipMemcpyAsync(dsel, sel.data(), sizeof(int) * take, hipMemcpyHostToDevice, s));
+  };
+
+  int fs = 0, kcols = 0, slot = 0;
+  if (variant == FEAST_METHOD_XFEAST) {  // step 0
+    copy_matrix(s, Xs, n, W, n, n, m0);
+    for (int b = 1; b < sx && !fs; ++b)
+      fs = filter_core(h, dt, n, m0, W + (size_t)(b - 1) * n * m0, n, W + (size_t)b * n * m0, n,
+                       Ac, ldac, nullptr, opt->refine_max);
+    kcols = K;
+  } else {  // step 1 of the first iteration
+    fs = filter_core(h, dt, n, m0, Xs, n, W, n, Ac, ldac, nullptr, opt->refine_max);
+  }
+  int st = fs ? fs : FEAST_NOT_CONVERGED;
+  int it = 0, prev_m = -1, mm = 0;
+  for (it = 1; fs == 0 && it <= opt->max_iter; ++it) {
+    int take = 0, me = -1, rs = 0, mcount = 0;
+    if (variant == FEAST_METHOD_XFEAST) {
+      int r = gram_orthonormal(h, n, kcols, W, U);  // step 1
+      rs = r < 0 ? FEAST_NONFINITE : r == 0 ? FEAST_B_NOT_SPD : 0;
+      if (!rs)
+        rs = rr_core(h, Ac, ldac, n, U, n, r, emin, emax, anorm, lam_h.data(), res_h.data(),
+                     &mcount, mixed ? Reig : nullptr, true);  // step 2.i
+      if (!rs) take = select_pairs(r, lam_h.data(), res_h.data(), emin, emax, m0, sel);  // 2.ii
+    } else {
+      kcols = m0;
+      for (int j = 1; j <= sx && !rs; ++j) {  // step 2
+        int r = gram_orthonormal(h, n, kcols, W, U);
+        rs = r < 0 ? FEAST_NONFINITE : r == 0 ? FEAST_B_NOT_SPD : 0;
+        if (!rs)
+          rs = rr_core(h, Ac, ldac, n, U, n, r, emin, emax, anorm, lam_h.data(), res_h.data(),
+                       &mcount, Reig, true);
+        if (rs) break;
+        take = select_pairs(r, lam_h.data(), res_h.data(), emin, emax, m0, sel);
+        if (j == 1) me = mcount;
+        if (j < sx) {  // step 2.iii: X' = [X' R]
+          upload_sel(take);
+          gather_columns(s, Reig, n, dsel, n, take, W + (size_t)kcols * n, n);
+          kcols += take;
+        }
+      }
+    }
+    if (rs) {
+      finish_timing(h);
+      st = rs;
+      break;
+    }
+    // X_{i+1}: the kept Ritz vectors (columns past `take` keep the previous block)
+    upload_sel(take);
+    gather_columns(s, U, n, dsel, n, take, Xs, n);
+    for (int a = 0; a < m0; ++a) {
+      lambda[a] = a < take ? lam_h[sel[a]] : INFINITY;
+      res[a] = a < take ? res_h[sel[a]] : INFINITY;
+    }
+    const bool seeded = mixed && take == m0;
+    if (seeded) {
+      gather_columns(s, Reig, n, dsel, n, take, Rsel, n);
+      gather_values(s, (const double*)h->b_lam.p, dsel, take, lsel);
+    }
+    RitzInfo ri{Rsel, lsel};
+    // rho(A) X_{i+1}: XFEAST's newest block (in place of the oldest), RFEAST's next X'
+    zd* dst = variant == FEAST_METHOD_XFEAST ? W + (size_t)slot * n * m0 : W;
+    auto filter_next = [&]() {
+      return filter_core(h, dt, n, m0, Xs, n, dst, n, Ac, ldac, seeded ? &ri : nullptr,
+                         opt->refine_max);
+    };
+    if (spur) {
+      fs = filter_next();
+      if (fs) {
+        st = fs;
+        break;
+      }
+      coldot_re(s, Xs, n, dst, n, n, take, dmu);
+      FEAST_HIP(hipMemcpyAsync(h->mu.data(), dmu, sizeof(double) * take, hipMemcpyDeviceToHost,
+                               s));
+      FEAST_HIP(hipStreamSynchronize(s));
+    }
+    finish_timing(h);
+    // step 3
+    std::vector<int> cand;
+    for (int a = 0; a < take; ++a) {
+      if (!(lambda[a] > emin && lambda[a] < emax)) continue;
+      if (spur && !(h->mu[a] > 0.5)) continue;
+      cand.push_back(a);
+    }
+    if (variant == FEAST_METHOD_RFEAST && !spur && me >= 0 && (int)cand.size() > me) {
+      std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) { return res[a] < res[b]; });
+      cand.resize(me);
+    }
+    double r = 0;
+    for (int a : cand) r = std::max(r, res[a]);
+    mm = (int)cand.size();
+    if (trace) trace[it - 1] = r;
+    if (mm == 0) {
+      if (prev_m == 0) {
+        st = FEAST_NO_EIGENVALUES;
+        break;
+      }
+    } else if (mm >= m0 && it >= 2) {
+      st = FEAST_M0_TOO_SMALL;
+      break;
+    } else if (r <= opt->tol) {
+      st = FEAST_OK;
+      break;
+    }
+    prev_m = mm;
+    if (!spur && it < opt->max_iter) {
+      fs = filter_next();
+      if (fs) {
+        st = fs;
+        break;
+      }
+    }
+    if (variant == FEAST_METHOD_XFEAST) slot = (slot + 1) % sx;  // step 4.ii
+  }
+  if (it > opt->max_iter) it = opt->max_iter;
+  *iters = it;
+  *m = mm;
+  if (dt == FEAST_R64) complex_to_real(s, Xs, n, (double*)X, ldx, n, m0);
+  else copy_matrix(s, Xs, n, (zd*)X, ldx, n, m0);
+  hipEvent_t t1 = h->timer.mark(s);
+  h->timer.add(t0, t1, P_TOTAL);
+  FEAST_HIP(hipStreamSynchronize(s));
+  finish_timing(h);
+  return st;
+}
 }  // namespace
 
 // =======================================================================================
@@ -772,7 +1041,11 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
   if (!opt || opt->n_c < 1 || opt->n_c > 128 || opt->m0 < 1 || opt->m0 > n ||
       opt->max_iter < 1 || !(opt->tol > 0) ||
       (opt->prec != FEAST_FP64 && opt->prec != FEAST_FP32_IR) ||
-      (opt->prec == FEAST_FP32_IR && opt->refine_max < 0))
+      (opt->prec == FEAST_FP32_IR && opt->refine_max < 0) ||
+      (opt->method != FEAST_METHOD_FEAST && opt->method != FEAST_METHOD_XFEAST &&
+       opt->method != FEAST_METHOD_RFEAST) ||
+      (opt->method != FEAST_METHOD_FEAST &&
+       (opt->expand < 1 || (long)opt->expand * opt->m0 > n)))
     return -8;
   if (!X) return -10;
   if (ldx < n) return -11;
@@ -785,16 +1058,11 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
     hipStream_t s = h->stream;
     h->timer.clear();
     hipEvent_t t0 = h->timer.mark(s);
-    long ldac;
-    const zd* Ac = complex_A(h, dt, n, A, lda, &ldac);
-    double anorm = opt->anorm;
-    if (!(anorm > 0)) {
-      zd* pw = h->b_pow.get<zd>(2 * (size_t)n);
-      double* dn = h->b_diag.get<double>(64);
-      anorm = norm2_estimate(s, Ac, ldac, n, 30, pw, dn);
-      if (!(anorm > 0)) anorm = 1.0;
-    }
-    int st = ensure_factors(h, dt, n, A, lda, emin, emax, opt->n_c, opt->prec);
+    long ldac = 0;
+    const zd* Ac = nullptr;
+    double anorm = 0;
+    zd* Xw = h->b_X0c.get<zd>((size_t)n * m0);
+    int st = solve_setup(h, dt, n, A, lda, emin, emax, opt, X0, ldx, &Ac, &ldac, &anorm, Xw);
     if (st) {
       FEAST_HIP(hipStreamSynchronize(s));
       finish_timing(h);
@@ -802,26 +1070,10 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
       *m = 0;
       return st;
     }
-    // working block (complex, n x m0)
-    zd* Xw = h->b_X0c.get<zd>((size_t)n * m0);
+    if (opt->method != FEAST_METHOD_FEAST)
+      return xr_solve(h, dt, n, Ac, ldac, anorm, emin, emax, opt, Xw, X, ldx, lambda, res, m,
+                      iters, trace, t0);
     zd* Qf = h->b_Qc.get<zd>((size_t)n * m0);
-    if (X0) {
-      if (dt == FEAST_R64) real_to_complex(s, (const double*)X0, ldx, Xw, n, n, m0);
-      else copy_matrix(s, (const zd*)X0, ldx, Xw, n, n, m0);
-    } else {
-      if (dt == FEAST_R64) {
-        double* tmp = (double*)h->b_Xc.get<zd>((size_t)n * m0);
-        gaussian_fill(s, tmp, n, n, m0, 1, opt->seed);
-        real_to_complex(s, tmp, n, Xw, n, n, m0);
-      } else {
-        gaussian_fill(s, Xw, n, n, m0, 0, opt->seed);
-      }
-    }
-    if (nonfinite_check(s, Xw, n, n, m0, h->b_flag.get<int>(64))) {
-      finish_timing(h);
-      *iters = 0;
-      return FEAST_NONFINITE;
-    }
     st = FEAST_NOT_CONVERGED;
     int it = 0, prev_m = -1, mm = 0;
     // FP32 factors leave the filtered block's damped directions (|rho| far below the FP32

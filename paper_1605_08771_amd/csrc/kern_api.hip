@@ -105,7 +105,7 @@ extern "C" int feast_kern_jacobi(const void* H, int m, double* d, void* W, void*
     FEAST_HIP(hipMalloc(&rank, sizeof(int) * mp));
     lam = d;
     copy_matrix(s, (const zd*)H, m, Hc, m, m, m);
-    int sweeps = jacobi_eigh(s, Hc, m, dd, V, work, flag, 60);
+    int sweeps = jacobi_eigh(s, Hc, m, dd, V, work, flag, 60, nullptr, mp);
     sort_eigen(s, dd, V, m, mp, lam, (zd*)W, rank);
     FEAST_HIP(hipStreamSynchronize(s));
     FEAST_HIP(hipFree(Hc));

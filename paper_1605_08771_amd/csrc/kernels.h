@@ -125,8 +125,13 @@ struct JacobiGraph {
   const void* flag = nullptr;
   ~JacobiGraph();
 };
+// mp = padded order (even, >= m; rows/columns beyond m are decoupled and sort last);
+// work: 3 mp^2, V: mp x mp (ld mp), d: mp.
 int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* dflag,
-                int max_sweeps, JacobiGraph* cache = nullptr);
+                int max_sweeps, JacobiGraph* cache, int mp);
+inline int jacobi_order(int m) { return m + (m & 1); }
+// A padded order on a coarse grid, so that recorded sweeps are reused across nearby sizes.
+inline int jacobi_order_quantized(int m) { return m <= 64 ? jacobi_order(m) : (m + 31) / 32 * 32; }
 // Stable ascending sort of d; Wout = V[:, order] (first m columns), lam = d[order].
 void sort_eigen(hipStream_t s, const double* d, const zd* V, int m, int mp, double* lam, zd* W,
                 int* rank);
@@ -157,5 +162,17 @@ void gaussian_fill(hipStream_t s, void* X, long ldx, int rows, int cols, int is_
 double norm2_estimate(hipStream_t s, const zd* A, long lda, int n, int iters, zd* work,
                       double* dnorm);
 int nonfinite_check(hipStream_t s, const zd* a, long ld, int rows, int cols, int* dflag);
+
+// ---- Expanded-subspace variants (xr.hip) ------------------------------------------------
+// B[:, c] /= ||B[:, c]||_2 for c < k (zero columns stay zero).
+void normalize_columns(hipStream_t s, zd* B, long ldb, int n, int k);
+// T (k x r, ld k) = V[:, keep[j]] / sqrt(d[keep[j]]), j < r.
+void gram_basis(hipStream_t s, const double* d, const zd* V, long ldv, const int* keep, int k,
+                int r, zd* T);
+// dst[:, a] = src[:, idx[a]] (n rows), a < cnt.
+void gather_columns(hipStream_t s, const zd* src, long lds, const int* idx, int n, int cnt, zd* dst,
+                    long ldd);
+// dst[a] = src[idx[a]], a < cnt.
+void gather_values(hipStream_t s, const double* src, const int* idx, int cnt, double* dst);
 
 }  // namespace feast

@@ -486,9 +486,9 @@ JacobiGraph::~JacobiGraph() {
 }
 
 int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* dflag,
-                int max_sweeps, JacobiGraph* cache) {
+                int max_sweeps, JacobiGraph* cache, int mp) {
   // work: 3 * mp * mp complex (A ping, A pong, V pong); V is mp x mp.
-  const int mp = m + (m & 1);
+  if (mp < jacobi_order(m) || (mp & 1)) mp = jacobi_order(m);
   zd* A0 = work;
   zd* A1 = work + (long)mp * mp;
   zd* V1 = work + 2L * mp * mp;
