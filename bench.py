@@ -190,6 +190,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the run in the other precision")
+    ap.add_argument("--variants", default=None,
+                    help="comma list of method:s runs of the Sec. 2 variants reported beside "
+                         "FEAST (default for c2: rfeast:2,rfeast:3,xfeast:2,xfeast:3; '' = none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -211,11 +214,11 @@ def main():
     f = fm.Feast()
     exact_in = np.sort(p.lam[(p.lam > p.emin) & (p.lam < p.emax)])
 
-    def one(tol, max_iter=p.max_iter, pr=None):
+    def one(tol, max_iter=p.max_iter, pr=None, method="feast", expand=1):
         f.invalidate()
         out = f.solve(A, p.emin, p.emax, p.m0, n_c=p.n_c, tol=tol, max_iter=max_iter,
                       anorm=p.anorm, X0=X0, prec=prec if pr is None else pr, spurious=True,
-                      refine_max=0)
+                      refine_max=0, method=method, expand=expand)
         return out
 
     def check(out, tol):
@@ -259,6 +262,7 @@ def main():
     solve = f.kernel_stats("solve")
     lu = f.kernel_stats("lu")
     rr = f.kernel_stats("rr")
+    eig_main = f.kernel_stats("eig")
     sides = 2
     alg_solve = sum(iters) * p.n_c * sides * 8.0 * p.n * p.n * p.m0
     achieved = alg_solve / (solve["ms"] * 1e-3) / 1e12 if solve["ms"] > 0 else 0.0
@@ -285,6 +289,33 @@ def main():
                    "phase_ms": {k: round(v, 2) for k, v in f.timings().items()},
                    "speedup_of_value_path": round(t_other / (total / args.steps), 3)}
         log(f"[bench] {other_name}: {compare}")
+    # the expanded-subspace variants of Sec. 2 on the same input and threshold
+    variants = []
+    vspec = args.variants
+    if vspec is None:
+        vspec = "rfeast:2,rfeast:3,xfeast:2,xfeast:3" if args.workload == "c2" else ""
+    for item in [v for v in vspec.split(",") if v]:
+        meth, sx = item.split(":")
+        sx = int(sx)
+        one(1e-10, max_iter=2, method=meth, expand=sx)  # buffers and recorded sweeps
+        f.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ov = one(1e-10, method=meth, expand=sx)
+        torch.cuda.synchronize()
+        tv = time.perf_counter() - t0
+        eig = f.kernel_stats("eig")
+        f.set_profiling(False)
+        okv, errv, resv = check(ov, 1e-10)
+        rec = {"method": meth, "expand": sx, "precision": prec_name, "time_s": round(tv, 4),
+               "iterations": ov["iters"], "correct": okv, "max_eig_err": errv,
+               "max_residual": resv,
+               "phase_ms": {k: round(v, 2) for k, v in f.timings().items()},
+               "eigensolves": {"ms": round(eig["ms"], 2), "sweeps": eig["launches"],
+                               "calls": int(eig["dense_flops"])},
+               "speedup_vs_feast": round((total / args.steps) / tv, 3)}
+        variants.append(rec)
+        log(f"[bench] variant {rec}")
     f.close()
 
     cpu = None
@@ -336,7 +367,10 @@ def main():
         "phase_ms_last_step": {k: round(v, 2) for k, v in phases[-1].items()},
         "lu_gemm_tflops": round(lu["dense_flops"] / (lu["ms"] * 1e-3) / 1e12, 2) if lu["ms"] else None,
         "rr_gemm_ms": round(rr["ms"], 2),
+        "eigensolves": {"ms": round(eig_main["ms"], 2), "sweeps": eig_main["launches"],
+                        "calls": int(eig_main["dense_flops"])},
         "other_precision": compare,
+        "variants": variants,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

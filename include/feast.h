@@ -212,7 +212,9 @@ int feast_get_timings(feast_handle h, double* out, int count);
  * 1 triangular-solve sweeps, 2 Rayleigh-Ritz, 3 refinement residual, 4 other.
  * feast_get_kernel_stats returns total kernel milliseconds, launch count and dense GEMM
  * flops (8 M N K per complex product) accumulated since profiling was enabled, summed over h
- * and its batch workers (whose kernels overlap in time). */
+ * and its batch workers (whose kernels overlap in time).  Class 5 covers the dense Hermitian
+ * eigensolves (Rayleigh-Ritz and the Gram matrices of XFEAST/RFEAST): milliseconds, Jacobi
+ * sweeps in place of launches, and the number of eigensolves in place of flops. */
 int feast_set_profiling(feast_handle h, int on);
 int feast_get_kernel_stats(feast_handle h, int kclass, double* total_ms, long long* launches,
                            double* dense_flops);

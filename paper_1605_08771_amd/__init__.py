@@ -23,7 +23,7 @@ FEAST_FP64, FEAST_FP32_IR = 0, 1
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "M0_TOO_SMALL", 3: "NO_EIGENVALUES",
           4: "B_NOT_SPD", 5: "NONFINITE", 6: "ZERO_PIVOT", -100: "ERR_ALLOC",
           -101: "ERR_HIP", -102: "ERR_UNSUPPORTED"}
-KCLASS = {"lu": 0, "solve": 1, "rr": 2, "refine": 3, "other": 4}
+KCLASS = {"lu": 0, "solve": 1, "rr": 2, "refine": 3, "other": 4, "eig": 5}
 
 
 METHODS = {"feast": 0, "xfeast": 1, "rfeast": 2}
@@ -118,6 +118,25 @@ def _ld(t, name):
     return t.stride(1)
 
 
+def _need(t, name, dtype, rows=None, cols=None):
+    """Refuse a tensor whose dtype, rank or shape does not match what the C-ABI will read or
+    write (the library trusts its pointers and sizes)."""
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    if rows is not None and t.shape[0] < rows:
+        raise ValueError(f"{name} has {t.shape[0]} rows, needs {rows}")
+    if cols is not None and t.shape[1] < cols:
+        raise ValueError(f"{name} has {t.shape[1]} columns, needs {cols}")
+
+
+def _square(A, name="A"):
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError(f"{name} must be square")
+    return A.shape[0]
+
+
 def _dtype_code(t):
     import torch
     if t.dtype == torch.complex128:
@@ -168,10 +187,13 @@ class Feast:
     def filter_apply(self, A, X, emin, emax, n_c, prec=FEAST_FP64, Q=None):
         import torch
         dt = _dtype_code(A)
+        n = _square(A)
+        _need(X, "X", A.dtype, rows=n)
         lda, ldx = _ld(A, "A"), _ld(X, "X")
-        n, m0 = X.shape
+        m0 = X.shape[1]
         if Q is None:
             Q = fortran(torch.empty((n, m0), dtype=X.dtype, device=X.device))
+        _need(Q, "Q", A.dtype, rows=n, cols=m0)
         ldq = _ld(Q, "Q")
         st = lib().feast_filter_apply(self.h, dt, n, _vp(A.data_ptr()), lda, emin, emax, n_c,
                                       prec, _vp(X.data_ptr()), ldx, m0, _vp(Q.data_ptr()), ldq)
@@ -181,8 +203,10 @@ class Feast:
         """Q is overwritten by the Ritz vectors. Returns (status, lam, res, m)."""
         import numpy as np
         dt = _dtype_code(A)
+        n = _square(A)
+        _need(Q, "Q", A.dtype, rows=n)
         lda, ldq = _ld(A, "A"), _ld(Q, "Q")
-        n, m0 = Q.shape
+        m0 = Q.shape[1]
         lam = np.zeros(m0)
         res = np.zeros(m0)
         m = ctypes.c_int(0)
@@ -201,12 +225,15 @@ class Feast:
         import torch
         dt = _dtype_code(A)
         lda = _ld(A, "A")
-        n = A.shape[0]
+        n = _square(A)
         if X is None:
             X = fortran(torch.empty((n, m0), dtype=A.dtype, device=A.device))
+        _need(X, "X", A.dtype, rows=n, cols=m0)
         ldx = _ld(X, "X")
-        if X0 is not None and _ld(X0, "X0") != ldx:
-            raise ValueError("X0 and X must share the leading dimension")
+        if X0 is not None:
+            _need(X0, "X0", A.dtype, rows=n, cols=m0)
+            if _ld(X0, "X0") != ldx:
+                raise ValueError("X0 and X must share the leading dimension")
         opts = FeastOpts(n_c=n_c, m0=m0, max_iter=max_iter, refine_max=refine_max, tol=tol,
                          anorm=anorm, prec=prec, seed=seed, spurious=int(spurious),
                          method=METHODS[method], expand=expand)
@@ -242,12 +269,18 @@ class Feast:
         outs = []
         for i, pr in enumerate(problems):
             A = pr["A"]
-            n = A.shape[0]
+            if _dtype_code(A) != dt:
+                raise TypeError("all problems of a batch must share one dtype")
+            n = _square(A)
             m0 = pr["m0"]
             X = fortran(torch.empty((n, m0), dtype=A.dtype, device=A.device))
             lam, res = np.zeros(m0), np.zeros(m0)
             m, it, st = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(-999)
             X0 = pr.get("X0")
+            if X0 is not None:
+                _need(X0, "X0", A.dtype, rows=n, cols=m0)
+                if _ld(X0, "X0") != _ld(X, "X"):
+                    raise ValueError("X0 must be column-major with leading dimension n")
             arr[i] = FeastProblem(n=n, lda=_ld(A, "A"), ldx=_ld(X, "X"), m0=m0,
                                   A=A.data_ptr(), emin=pr["emin"], emax=pr["emax"],
                                   anorm=pr.get("anorm", 0.0),
@@ -270,12 +303,18 @@ class Feast:
     def gemm(self, opA, opB, A, B, C, alpha=1.0, beta=0.0, M=None, N=None, K=None):
         """C = alpha op(A) op(B) + beta C on the matrix cores (complex128 or complex64)."""
         import torch
+        if A.dtype not in (torch.complex128, torch.complex64):
+            raise TypeError("gemm takes complex128 or complex64 operands")
         prec = 0 if A.dtype == torch.complex128 else 1
-        lda, ldb, ldc = _ld(A, "A"), _ld(B, "B"), _ld(C, "C")
         M = C.shape[0] if M is None else M
         N = C.shape[1] if N is None else N
         if K is None:
             K = A.shape[1] if opA == 0 else A.shape[0]
+        if K > 0:
+            _need(A, "A", A.dtype, *((M, K) if opA == 0 else (K, M)))
+            _need(B, "B", A.dtype, *((K, N) if opB == 0 else (N, K)))
+        _need(C, "C", A.dtype, M, N)
+        lda, ldb, ldc = _ld(A, "A"), _ld(B, "B"), _ld(C, "C")
         al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
         be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
         st = lib().feast_kern_gemm(prec, opA, opB, M, N, K, al, _vp(A.data_ptr()), lda,
@@ -288,8 +327,9 @@ class Feast:
         (status, LU [nc, np, np] tensor in column-major blocks, perm [nc, np])."""
         import numpy as np
         import torch
+        _need(A, "A", torch.complex128)
+        n = _square(A)
         lda = _ld(A, "A")
-        n = A.shape[0]
         zz = np.ascontiguousarray(np.asarray(z, dtype=np.complex128)).view(np.float64)
         nc = len(zz) // 2
         npo = ctypes.c_int()
@@ -307,7 +347,10 @@ class Feast:
 
     def jacobi(self, H):
         import torch
-        m = H.shape[0]
+        _need(H, "H", torch.complex128)
+        m = _square(H, "H")
+        if H.device.type != "cuda":
+            raise ValueError("H must live on the HIP device")
         Hf = fortran(H)
         d = torch.empty(m, dtype=torch.float64, device=H.device)
         W = fortran(torch.empty((m, m), dtype=H.dtype, device=H.device))

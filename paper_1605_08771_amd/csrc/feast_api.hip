@@ -110,8 +110,8 @@ struct EventPool {
   }
 };
 
-constexpr int NCLASS = 5;
-enum { K_LU = 0, K_SOLVE = 1, K_RR = 2, K_REFINE = 3, K_OTHER = 4 };
+constexpr int NCLASS = 6;
+enum { K_LU = 0, K_SOLVE = 1, K_RR = 2, K_REFINE = 3, K_OTHER = 4, K_EIG = 5 };
 
 struct KernelProfiler : GemmProfiler {
   bool on = false;
@@ -135,7 +135,17 @@ struct KernelProfiler : GemmProfiler {
     FEAST_HIP(hipEventRecord(b, s));
     pending.push_back({cur_a, b, cls, f});
   }
+  // An eigensolve: its time (events a..b), sweeps counted as launches, one per call as flops.
+  std::vector<std::pair<long long, int>> eig_pending;
+  void eig(hipStream_t s, hipEvent_t a, int sweeps) {
+    hipEvent_t b = pool.take();
+    FEAST_HIP(hipEventRecord(b, s));
+    pending.push_back({a, b, K_EIG, 1.0});
+    eig_pending.push_back({(long long)std::max(sweeps, 0), 1});
+  }
   void flush() {  // stream must be synchronised
+    for (auto& e : eig_pending) launches[K_EIG] += e.first - 1;
+    eig_pending.clear();
     for (auto& r : pending) {
       float t = 0;
       FEAST_HIP(hipEventElapsedTime(&t, r.a, r.b));
@@ -554,7 +564,10 @@ int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m
   zd* V = h->b_V.get<zd>((size_t)mp * mp);
   zd* jw = h->b_jac.get<zd>(3 * (size_t)mp * mp);
   int* dflag = h->b_flag.get<int>(64);
+  hipEvent_t ej = h->prof.on ? h->prof.pool.take() : nullptr;
+  if (ej) FEAST_HIP(hipEventRecord(ej, s));
   int sweeps = jacobi_eigh(s, H, m0, d, V, jw, dflag, 40, &h->jgraphs[mp], mp);
+  if (ej) h->prof.eig(s, ej, sweeps);
   (void)sweeps;
   double* lam = h->b_lam.get<double>(mp);
   zd* W = h->b_W.get<zd>((size_t)m0 * m0);
@@ -648,7 +661,10 @@ int gram_orthonormal(feast_ctx* h, int n, int k, zd* B, zd* U) {
   zd* V = h->b_V.get<zd>((size_t)mp * mp);
   zd* jw = h->b_jac.get<zd>(3 * (size_t)mp * mp);
   int* dflag = h->b_flag.get<int>(64);
-  jacobi_eigh(s, G, k, d, V, jw, dflag, 40, &h->jgraphs[mp], mp);
+  hipEvent_t ej = h->prof.on ? h->prof.pool.take() : nullptr;
+  if (ej) FEAST_HIP(hipEventRecord(ej, s));
+  int sweeps = jacobi_eigh(s, G, k, d, V, jw, dflag, 40, &h->jgraphs[mp], mp);
+  if (ej) h->prof.eig(s, ej, sweeps);
   std::vector<double> hd(k);
   FEAST_HIP(hipMemcpyAsync(hd.data(), d, sizeof(double) * k, hipMemcpyDeviceToHost, s));
   FEAST_HIP(hipStreamSynchronize(s));

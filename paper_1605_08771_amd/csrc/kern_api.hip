@@ -93,7 +93,7 @@ extern "C" int feast_kern_jacobi(const void* H, int m, double* d, void* W, void*
   if (!W) return -4;
   try {
     hipStream_t s = (hipStream_t)hip_stream;
-    const int mp = m + (m & 1);
+    const int mp = jacobi_order(m);
     zd *Hc, *V, *work;
     double *dd, *lam;
     int *flag, *rank;

@@ -111,8 +111,8 @@ void cholesky_upper(hipStream_t s, zd* G, int m, int ldg, int* flag, zd* tmp);
 // Rinv = R^{-1} for upper triangular R (m x m); Rinv must be zeroed by the call.
 void upper_inverse(hipStream_t s, const zd* R, int m, int ldr, zd* Rinv, int ldi, zd* tmp);
 // Cyclic parallel-order Jacobi on the Hermitian m x m matrix H (ld = m, destroyed).
-// Returns sweeps used (host sync per sweep) or -1.  d (device, m) eigenvalues unsorted,
-// V (device, m x m) eigenvectors.
+// Returns sweeps used (host sync per sweep) or -1.  d (device, mp) eigenvalues unsorted,
+// V (device, mp x mp, ld mp) eigenvectors; work: 3 mp^2 complex.
 // One sweep is recorded as a HIP graph (rounds, then a fill kernel and the check: no memset
 // node) and replayed per sweep when cache is given; the graph is re-recorded when the sizes
 // or buffers change.
@@ -125,8 +125,7 @@ struct JacobiGraph {
   const void* flag = nullptr;
   ~JacobiGraph();
 };
-// mp = padded order (even, >= m; rows/columns beyond m are decoupled and sort last);
-// work: 3 mp^2, V: mp x mp (ld mp), d: mp.
+// mp = padded order (even, >= m; rows/columns beyond m are decoupled and sort last).
 int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* dflag,
                 int max_sweeps, JacobiGraph* cache, int mp);
 inline int jacobi_order(int m) { return m + (m & 1); }

@@ -175,3 +175,20 @@ def test_batched_argument_checks():
     assert f(BAD, 1, 1, arr, ctypes.byref(o), 0) == -6
     assert f(BAD, 1, 1, arr, ctypes.byref(o), 33) == -6
     assert f(BAD, 1, 0, arr, ctypes.byref(o), 4) == 0
+
+
+def test_binding_refuses_mismatched_tensors():
+    """The C-ABI trusts pointers and sizes, so the binding refuses tensors whose dtype or shape
+    differs from what the call will read or write (checked before any library call)."""
+    import torch
+    with pytest.raises(TypeError):
+        fm._need(torch.zeros(4, 4, dtype=torch.float64), "H", torch.complex128)
+    with pytest.raises(ValueError):
+        fm._need(torch.zeros(3, 2, dtype=torch.complex128), "X", torch.complex128, rows=4)
+    with pytest.raises(ValueError):
+        fm._need(torch.zeros(4, 2, dtype=torch.complex128), "X", torch.complex128, cols=3)
+    with pytest.raises(ValueError):
+        fm._square(torch.zeros(4, 3, dtype=torch.complex128))
+    fm._need(torch.zeros(4, 3, dtype=torch.complex128), "X", torch.complex128, rows=4, cols=3)
+    with pytest.raises(TypeError):
+        fm._dtype_code(torch.zeros(2, 2, dtype=torch.float32))

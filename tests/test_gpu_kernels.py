@@ -109,7 +109,7 @@ def test_batched_lu(fe, n, prec):
         assert be < 5.0, (j, be)
 
 
-@pytest.mark.parametrize("m", [1, 2, 7, 64, 75, 301])
+@pytest.mark.parametrize("m", [1, 2, 7, 31, 33, 64, 75, 301, 512, 513, 900])
 def test_jacobi_vs_lapack(fe, m):
     import torch
     rng = np.random.default_rng(m)
@@ -121,6 +121,54 @@ def test_jacobi_vs_lapack(fe, m):
     d = d.cpu().numpy()
     W = W.cpu().numpy()
     scale = np.linalg.norm(H, 2)
-    np.testing.assert_allclose(d, np.linalg.eigvalsh(H), rtol=0, atol=1e-13 * scale)
-    np.testing.assert_allclose(W.conj().T @ W, np.eye(m), rtol=0, atol=1e-13)
-    np.testing.assert_allclose(H @ W, W * d, rtol=0, atol=1e-13 * scale)
+    tol = max(1e-13, 4 * m * np.finfo(float).eps)  # a small multiple of m eps ||H||_2
+    np.testing.assert_allclose(d, np.linalg.eigvalsh(H), rtol=0, atol=tol * scale)
+    np.testing.assert_allclose(W.conj().T @ W, np.eye(m), rtol=0, atol=tol)
+    np.testing.assert_allclose(H @ W, W * d, rtol=0, atol=tol * scale)
+
+
+@pytest.mark.parametrize("m", [96, 600])
+def test_jacobi_gram_spectrum(fe, m):
+    """A Gram matrix B^H B whose eigenvalues fall from 1 to 1e-16 (the orthogonalization of
+    the expanded subspaces): eigenvalues to 1e-13 ||G|| absolutely, and the eigenvectors of the
+    eigenvalues above 1e-8 span LAPACK's invariant subspace."""
+    import torch
+    from tests.pins import sin_theta_max
+    rng = np.random.default_rng(m + 7)
+    Q, _ = np.linalg.qr(_crand(rng, m, m))
+    ev = np.logspace(0, -16, m)
+    G = (Q * ev) @ Q.conj().T
+    G = 0.5 * (G + G.conj().T)
+    sweeps, d, W = fe.jacobi(torch.from_numpy(G).cuda())
+    torch.cuda.synchronize()
+    assert sweeps >= 0
+    d = d.cpu().numpy()
+    W = W.cpu().numpy()
+    dr, Wr = np.linalg.eigh(G)
+    np.testing.assert_allclose(d, dr, rtol=0, atol=1e-13)
+    big = dr > 1e-8
+    assert sin_theta_max(Wr[:, big], W[:, d > 1e-8]) < 1e-6
+    # a graded spectrum takes ~3x the sweeps of a random one; each rotation is unitary to one
+    # rounding error, so orthonormality is held to a multiple of m eps
+    np.testing.assert_allclose(W.conj().T @ W, np.eye(m), rtol=0, atol=max(1e-13, 8 * m * 2.2e-16))
+
+
+def test_binding_refuses_real_input_to_complex_calls(fe):
+    """A real tensor handed to a complex-only building block is refused before any launch."""
+    import torch
+    H = torch.eye(8, dtype=torch.float64, device="cuda")
+    with pytest.raises(TypeError):
+        fe.jacobi(H)
+    with pytest.raises(TypeError):
+        fe.lu(H, np.array([1j]))
+    A = fm_fortran(torch.eye(8, dtype=torch.complex128, device="cuda"))
+    Xr = fm_fortran(torch.zeros(8, 2, dtype=torch.float64, device="cuda"))
+    with pytest.raises(TypeError):
+        fe.filter_apply(A, Xr, -1.0, 1.0, 4)
+    with pytest.raises(TypeError):
+        fe.solve(A, -1.0, 1.0, 2, X0=Xr)
+
+
+def fm_fortran(t):
+    import paper_1605_08771_amd as fm
+    return fm.fortran(t)
