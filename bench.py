@@ -33,6 +33,21 @@ PEAK_FP32_MFMA = 157.3
 PEAK_HBM = 8000.0      # GB/s
 
 
+# HBM bytes per launch of the paired sweep GEMM on the default workload (FP64, n=8192), from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy of known size; valid only
+# while the sources of that kernel are the ones the counters were taken on.
+SWEEP_TRAFFIC = {"sources": "6df62ef4736f4d94", "bytes_per_launch": 5.244e8}
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gemm.hip", "solve.hip", "kernels.h", "common.h"):
+        with open(os.path.join(ROOT, "paper_1605_08771_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -41,7 +56,7 @@ def make_problem(args, dev):
     from paper_1605_08771_amd import gen
     t0 = time.time()
     if args.workload == "c2":
-        p = gen.config2(n=args.n or 8192, device=dev)
+        p = gen.config2(n=args.n or 8192, device=dev, basis=args.basis)
     elif args.workload == "c3":
         p = gen.config3(n=args.n or 16384, device=dev)
     elif args.workload == "c5":
@@ -151,6 +166,11 @@ def bench_batched(args, dev):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t1
     f.close()
+    traffic = None
+    if (args.workload == "c2" and p.n == 8192 and prec == fm.FEAST_FP64
+            and kernel_sources_hash() == SWEEP_TRAFFIC["sources"]):
+        traffic = SWEEP_TRAFFIC["bytes_per_launch"]
+
     line = {
         "metric": METRIC, "value": round(total / args.steps, 4), "unit": "s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
@@ -190,6 +210,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the run in the other precision")
+    ap.add_argument("--basis", default="haar", choices=["haar", "householder"],
+                    help="c2 eigenvectors: QR of a Gaussian matrix (default) or 8 dense "
+                         "reflectors built without library factorizations (for counter runs)")
     ap.add_argument("--variants", default=None,
                     help="comma list of method:s runs of the Sec. 2 variants reported beside "
                          "FEAST (default for c2: rfeast:2,rfeast:3,xfeast:2,xfeast:3; '' = none)")
@@ -264,11 +287,18 @@ def main():
     rr = f.kernel_stats("rr")
     eig_main = f.kernel_stats("eig")
     sides = 2
-    alg_solve = sum(iters) * p.n_c * sides * 8.0 * p.n * p.n * p.m0
+    # filter applications: one per iteration plus the one that gives the last iterate's
+    # filter values mu_k (the spurious-pair test is on)
+    n_filters = sum(iters) + args.steps
+    alg_solve = n_filters * p.n_c * sides * 8.0 * p.n * p.n * p.m0
+    # algorithmic HBM bytes of the sweeps: each factor read once per sweep (forward and
+    # backward; the two sides read complementary triangles) and each right-hand-side block
+    # read and written once per sweep
+    alg_solve_bytes = n_filters * p.n_c * 2 * (16.0 * p.n * p.n + sides * 2 * 16.0 * p.n * p.m0)
     achieved = alg_solve / (solve["ms"] * 1e-3) / 1e12 if solve["ms"] > 0 else 0.0
     peak = PEAK_FP64_MFMA if prec == fm.FEAST_FP64 else PEAK_FP32_MFMA
     filt_ms = sum(ph["solve_ms"] + ph["accumulate_ms"] for ph in phases)
-    alg_filter = alg_solve + sum(iters) * p.n_c * sides * 8.0 * p.n * p.m0
+    alg_filter = alg_solve + n_filters * p.n_c * sides * 8.0 * p.n * p.m0
     filter_tflops = alg_filter / (filt_ms * 1e-3) / 1e12 if filt_ms > 0 else 0.0
     f.set_profiling(False)
 
@@ -352,10 +382,13 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes/launch",
             "launches": solve["launches"],
             "avg_launch_ms": round(solve["ms"] / max(1, solve["launches"]), 5),
             "algorithmic_flops_per_launch": alg_solve / max(1, solve["launches"]),
+            "algorithmic_bytes_per_launch": alg_solve_bytes / max(1, solve["launches"]),
+            "filter_applications": n_filters,
         },
         "filter_apply_tflops": round(filter_tflops, 2),
         "iterations": iters,

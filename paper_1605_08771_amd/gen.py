@@ -138,8 +138,40 @@ def gaussian_block(rng, n, m0, complex_, device=None):
     return torch.from_numpy(x).to(device).mT.contiguous().mT
 
 
-def make_problem(lam, emin, emax, m0, n_c, tol, max_iter, complex_, rng, device=None, name=""):
+def householder_assemble(rng, lam, complex_, device, k=8):
+    """A = H_k ... H_1 diag(lam) H_1 ... H_k with k seeded dense reflectors H = I - 2 v v^H
+    (|v| = 1), built with elementwise products and row sums only (no library factorization or
+    matrix product).  The same eigenvalues and dense storage as the Haar construction, with
+    eigenvectors U = H_k ... H_1 (not formed).  Device tensors only."""
+    import torch
     n = len(lam)
+    dt = torch.complex128 if complex_ else torch.float64
+    A = torch.diag(torch.from_numpy(np.asarray(lam, dtype=np.float64)).to(device)).to(dt)
+    for _ in range(k):
+        v = rng.standard_normal(n)
+        if complex_:
+            v = v + 1j * rng.standard_normal(n)
+        v = torch.from_numpy(v / np.linalg.norm(v)).to(device=device, dtype=dt)
+        w = (A * v[None, :]).sum(dim=1)                       # A v
+        c = (v.conj() * w).sum()                              # v^H A v
+        A = A - 2 * (v[:, None] * w.conj()[None, :]) - 2 * (w[:, None] * v.conj()[None, :]) \
+            + 4 * c * (v[:, None] * v.conj()[None, :])
+    A = 0.5 * (A + A.conj().T)
+    return A.mT.contiguous().mT
+
+
+def make_problem(lam, emin, emax, m0, n_c, tol, max_iter, complex_, rng, device=None, name="",
+                 basis="haar"):
+    """basis "haar" (default): U from the QR of a Gaussian matrix, kept in the result;
+    "householder" (device only): the reflector construction, U not formed (None)."""
+    n = len(lam)
+    if basis == "householder":
+        A = householder_assemble(rng, lam, complex_, device)
+        X0 = gaussian_block(rng, n, m0, complex_, device)
+        m_true = int(np.sum((lam > emin) & (lam < emax)))
+        return Problem(n=n, dtype="c128" if complex_ else "r64", emin=emin, emax=emax, m0=m0,
+                       n_c=n_c, tol=tol, max_iter=max_iter, lam=np.asarray(lam), m_true=m_true,
+                       anorm=float(np.max(np.abs(lam))), A=A, U=None, X0=X0, name=name)
     U = haar_basis(rng, n, complex_, device)
     A = assemble(lam, U, device)
     X0 = gaussian_block(rng, n, m0, complex_, device)
@@ -180,14 +212,15 @@ def config1(n=500, device=None, seed_tag=1):
 
 
 def config2(n=8192, device=None, seed_tag=2, n_in=200, n_in_edge=40, n_out_edge=100, m0=300,
-            n_c=8, half_width=0.05, max_iter=200):
+            n_c=8, half_width=0.05, max_iter=200, basis="haar"):
     """Complex Hermitian hard case: n_in eigenvalues in I = (-0.05, 0.05) with n_in_edge
     within 1e-3 inside each endpoint, n_out_edge within 1e-3 outside each endpoint, the rest
     uniform on [-1, 1] outside the clusters; m0 = 300, n_c = 8, tol 1e-12."""
     rng = rng_for(seed_tag)
     emin, emax = -half_width, half_width
     lam = edge_cluster_spectrum(rng, n, emin, emax, n_in_edge, n_out_edge, n_in)
-    return make_problem(lam, emin, emax, m0, n_c, 1e-12, max_iter, True, rng, device, "C2")
+    return make_problem(lam, emin, emax, m0, n_c, 1e-12, max_iter, True, rng, device, "C2",
+                        basis=basis)
 
 
 def config3(n=16384, device=None, seed_tag=3):
