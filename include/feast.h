@@ -183,6 +183,8 @@ typedef struct {
   int* m;            /* host */
   int* iters;        /* host */
   int* status;       /* host: the feast_solve return code of this problem */
+  double* mu;        /* host, m0, or NULL: filter values mu_k of the returned Ritz vectors
+                        (written when opt->spurious = 1 or opt->prec = FEAST_FP32_IR) */
 } feast_problem;
 
 /* Independent FEAST problems (Sec. 1: disjoint intervals, or independent matrices, are solved

@@ -58,6 +58,10 @@ def lib():
         L.or_feast_solve_ex.argtypes = L.or_feast_solve.argtypes + [ctypes.c_int, _dp]
         L.or_xrfeast_solve.argtypes = [ctypes.c_int] + L.or_feast_solve.argtypes[:7] + [
             ctypes.c_int, ctypes.c_int] + L.or_feast_solve.argtypes[8:] + [ctypes.c_int, _dp]
+        L.or_feast_solve_gen.argtypes = L.or_feast_solve.argtypes[:4] + [_dp, ctypes.c_int] + \
+            L.or_feast_solve.argtypes[4:] + [ctypes.c_int, _dp]
+        L.or_filter_apply_gen.argtypes = L.or_filter_apply.argtypes[:4] + [_dp, ctypes.c_int] + \
+            L.or_filter_apply.argtypes[4:]
         L.or_select_pairs.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_int, _ip]
         L.or_num_threads.restype = ctypes.c_int
@@ -179,6 +183,46 @@ def feast_solve(dtype, A, emin, emax, nc, m0, tol, max_iter, anorm, X0, spurious
                                  anorm, _ptr(X0), n, _ptr(X), n, _ptr(lam), _ptr(res),
                                  ctypes.byref(m), ctypes.byref(iters), _ptr(trace),
                                  int(spurious), _ptr(mu))
+    out = dict(status=st, X=X, lam=lam, res=res, m=m.value, iters=iters.value,
+               trace=trace[: iters.value])
+    if spurious:
+        out["mu"] = mu
+    return out
+
+
+def filter_apply_gen(dtype, A, B, emin, emax, nc, X):
+    """Q = rho(B^{-1} A) X for the Hermitian-definite pencil (A, B)."""
+    A = _fort(A, dtype)
+    B = _fort(B, dtype)
+    X = _fort(X, dtype)
+    n, m0 = X.shape
+    Q = np.zeros((n, m0), dtype=A.dtype, order="F")
+    st = lib().or_filter_apply_gen(_dt(dtype), n, _ptr(A), n, _ptr(B), n, emin, emax, nc,
+                                   _ptr(X), n, m0, _ptr(Q), n)
+    if st:
+        raise RuntimeError(f"oracle filter_apply_gen status {st}")
+    return Q
+
+
+def feast_solve_gen(dtype, A, B, emin, emax, nc, m0, tol, max_iter, anorm, X0, spurious=False):
+    """FEAST on A x = lambda B x (B Hermitian positive definite); B=None is B = I.  Ritz
+    vectors are B-normalized and res_k = ||A x_k - lambda_k B x_k|| / anorm."""
+    A = _fort(A, dtype)
+    X0 = _fort(X0, dtype)
+    Bf = _fort(B, dtype) if B is not None else None
+    n = A.shape[0]
+    X = np.zeros((n, m0), dtype=A.dtype, order="F")
+    lam = np.zeros(m0)
+    res = np.zeros(m0)
+    m = ctypes.c_int(0)
+    iters = ctypes.c_int(0)
+    trace = np.zeros(max_iter)
+    mu = np.zeros(m0)
+    st = lib().or_feast_solve_gen(_dt(dtype), n, _ptr(A), n,
+                                  _ptr(Bf) if Bf is not None else None, n, emin, emax, nc, m0,
+                                  tol, max_iter, anorm, _ptr(X0), n, _ptr(X), n, _ptr(lam),
+                                  _ptr(res), ctypes.byref(m), ctypes.byref(iters), _ptr(trace),
+                                  int(spurious), _ptr(mu))
     out = dict(status=st, X=X, lam=lam, res=res, m=m.value, iters=iters.value,
                trace=trace[: iters.value])
     if spurious:

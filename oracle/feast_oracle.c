@@ -322,7 +322,9 @@ static void factors_free(factors_t* f) {
   memset(f, 0, sizeof(*f));
 }
 
-static int factors_build(factors_t* f, const zc* A, int n, double emin, double emax, int nc) {
+/* Bm == NULL: the standard problem (B = I). */
+static int factors_build(factors_t* f, const zc* A, const zc* Bm, int n, double emin,
+                         double emax, int nc) {
   f->n = n; f->nc = nc;
   f->z = malloc(sizeof(zc) * nc);
   f->omega = malloc(sizeof(zc) * nc);
@@ -334,8 +336,12 @@ static int factors_build(factors_t* f, const zc* A, int n, double emin, double e
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
   for (int j = 0; j < nc; j++) {
     zc* M = f->lu + (size_t)j * n * n;
-    for (size_t k = 0; k < (size_t)n * n; k++) M[k] = -A[k]; /* M = z_j I - A */
-    for (int i = 0; i < n; i++) M[i + (size_t)i * n] += f->z[j];
+    if (Bm) {
+      for (size_t k = 0; k < (size_t)n * n; k++) M[k] = f->z[j] * Bm[k] - A[k]; /* z_j B - A */
+    } else {
+      for (size_t k = 0; k < (size_t)n * n; k++) M[k] = -A[k]; /* M = z_j I - A */
+      for (int i = 0; i < n; i++) M[i + (size_t)i * n] += f->z[j];
+    }
     if (zlu(n, M, n, f->piv + (size_t)j * n) != 0) bad = 1;
   }
   return bad ? 6 : 0;
@@ -389,7 +395,7 @@ int or_filter_apply(int dtype, int n, const double* A, int lda, double emin, dou
   zc* Xz = load_matrix(dtype, n, m0, X, ldx);
   factors_t f;
   memset(&f, 0, sizeof(f));
-  int st = factors_build(&f, Az, n, emin, emax, nc);
+  int st = factors_build(&f, Az, NULL, n, emin, emax, nc);
   if (st == 0) {
     zc* Qz = malloc(sizeof(zc) * (size_t)n * m0);
     filter_with_factors(&f, dtype, Xz, m0, Qz);
@@ -428,16 +434,17 @@ static void hermitize(int m, zc* H) {
 }
 
 /* Appendix, FEAST step 2 (and step 3's residuals).  In: Q = X' (n x m0 basis).
- * Out: Q = Ritz vectors x_k (unit 2-norm, ascending lambda), lambda, res_k =
- * ||A x_k - lambda_k x_k|| / anorm, m = #{lambda_k in (emin, emax)}.
- *   A' = X'^H A X',  B' = X'^H X'  (both made exactly Hermitian)
+ * Out: Q = Ritz vectors x_k (unit B-norm, ascending lambda), lambda, res_k =
+ * ||A x_k - lambda_k B x_k|| / anorm, m = #{lambda_k in (emin, emax)}.  Bm == NULL: B = I.
+ *   A' = X'^H A X',  B' = X'^H B X'  (both made exactly Hermitian)
  *   B' = V S^2 V^H (Jacobi), T = V S^{-1}   [Sec. 2, Method 1: U = X' V S^{-1}]
  *   C = T^H A' T = Z Lambda Z^H (Jacobi), W = T Z  solves A' W = B' W Lambda
  *   X = X' W.                                                                            */
-static int rr_core(int n, const zc* A, zc* Qb, int m0, double emin, double emax, double anorm,
-                   double* lambda, double* res, int* m) {
+static int rr_core(int n, const zc* A, const zc* Bm, zc* Qb, int m0, double emin, double emax,
+                   double anorm, double* lambda, double* res, int* m) {
   int st = 0;
   zc* AQ = malloc(sizeof(zc) * (size_t)n * m0);
+  zc* BQ = malloc(sizeof(zc) * (size_t)n * m0);
   zc* Ap = malloc(sizeof(zc) * (size_t)m0 * m0);
   zc* Bp = malloc(sizeof(zc) * (size_t)m0 * m0);
   zc* V = malloc(sizeof(zc) * (size_t)m0 * m0);
@@ -453,7 +460,12 @@ static int rr_core(int n, const zc* A, zc* Qb, int m0, double emin, double emax,
 
   matmul(0, n, m0, n, A, n, Qb, n, AQ);   /* A X'        */
   matmul(1, m0, m0, n, Qb, n, AQ, n, Ap); /* X'^H A X'   */
-  matmul(1, m0, m0, n, Qb, n, Qb, n, Bp); /* X'^H X'     */
+  if (Bm && g_fault != 11) { /* planted (11): B' = X'^H X' whatever B */
+    matmul(0, n, m0, n, Bm, n, Qb, n, BQ);
+    matmul(1, m0, m0, n, Qb, n, BQ, n, Bp); /* X'^H B X' */
+  } else {
+    matmul(1, m0, m0, n, Qb, n, Qb, n, Bp); /* X'^H X'     */
+  }
   hermitize(m0, Ap);
   hermitize(m0, Bp);
   if (!all_finite(Ap, (size_t)m0 * m0) || !all_finite(Bp, (size_t)m0 * m0)) { st = 5; goto done; }
@@ -480,13 +492,16 @@ static int rr_core(int n, const zc* A, zc* Qb, int m0, double emin, double emax,
     while (i >= 0 && lam[order[i]] > lam[v]) { order[i + 1] = order[i]; i--; }
     order[i + 1] = v;
   }
+  /* B x for the normalization x^H B x = 1 (2-norm when B = I) */
+  if (Bm) matmul(0, n, m0, n, Bm, n, Xn, n, BQ);
   int cnt = 0;
   for (int k = 0; k < m0; k++) {
     int src = order[k];
     double nrm = 0.0;
     for (int i = 0; i < n; i++) {
       zc v = Xn[i + (size_t)src * n];
-      nrm += creal(v) * creal(v) + cimag(v) * cimag(v);
+      if (Bm) nrm += creal(conj(v) * BQ[i + (size_t)src * n]);
+      else nrm += creal(v) * creal(v) + cimag(v) * cimag(v);
     }
     nrm = sqrt(nrm);
     for (int i = 0; i < n; i++) Qb[i + (size_t)k * n] = Xn[i + (size_t)src * n] / nrm;
@@ -494,12 +509,15 @@ static int rr_core(int n, const zc* A, zc* Qb, int m0, double emin, double emax,
     if (lambda[k] > emin && lambda[k] < emax) cnt++;
   }
   *m = cnt;
-  /* residuals r_k = || A x_k - lambda_k x_k ||_2 / anorm (Appendix, FEAST step 3) */
+  /* residuals r_k = || A x_k - lambda_k B x_k ||_2 / anorm (Appendix, FEAST step 3) */
   matmul(0, n, m0, n, A, n, Qb, n, AQ);
+  if (Bm) matmul(0, n, m0, n, Bm, n, Qb, n, BQ);
   for (int k = 0; k < m0; k++) {
     double s = 0.0;
     for (int i = 0; i < n; i++) {
-      zc r = AQ[i + (size_t)k * n] - lambda[k] * Qb[i + (size_t)k * n];
+      zc bx = (Bm && g_fault != 10) ? BQ[i + (size_t)k * n] /* planted (10): B dropped */
+                                    : Qb[i + (size_t)k * n];
+      zc r = AQ[i + (size_t)k * n] - lambda[k] * bx;
       s += creal(r) * creal(r) + cimag(r) * cimag(r);
     }
     res[k] = sqrt(s) / anorm;
@@ -507,7 +525,7 @@ static int rr_core(int n, const zc* A, zc* Qb, int m0, double emin, double emax,
   for (int k = 0; k < m0; k++)
     if (!isfinite(lambda[k]) || !isfinite(res[k])) st = 5;
 done:
-  free(AQ); free(Ap); free(Bp); free(V); free(T); free(TA); free(C); free(Z); free(W);
+  free(AQ); free(BQ); free(Ap); free(Bp); free(V); free(T); free(TA); free(C); free(Z); free(W);
   free(Xn); free(s2); free(lam); free(order);
   return st;
 }
@@ -526,7 +544,7 @@ int or_rayleigh_ritz(int dtype, int n, const double* A, int lda, double* Q, int 
   if (!lambda || !res || !m) return -11;
   zc* Az = load_matrix(dtype, n, n, A, lda);
   zc* Qz = load_matrix(dtype, n, m0, Q, ldq);
-  int st = rr_core(n, Az, Qz, m0, emin, emax, anorm, lambda, res, m);
+  int st = rr_core(n, Az, NULL, Qz, m0, emin, emax, anorm, lambda, res, m);
   if (st == 0) store_matrix(dtype, n, m0, Qz, Q, ldq);
   free(Az);
   free(Qz);
@@ -544,53 +562,43 @@ int or_rayleigh_ritz(int dtype, int n, const double* A, int lda, double* Q, int 
  * rho > 1/2 exactly on I; a Ritz vector made of eigenvectors outside I has mu < 1/2.  mu_k is
  * computed by applying the filter to the Ritz vectors, which is also the next iteration's
  * step 1.  mu_out (nullable) receives mu of the returned Ritz vectors (spurious = 1).      */
-int or_feast_solve_ex(int dtype, int n, const double* A, int lda, double emin, double emax,
-                      int nc, int m0, double tol, int max_iter, double anorm, const double* X0,
-                      int ldx0, double* X, int ldx, double* lambda, double* res, int* m,
-                      int* iters, double* trace, int spurious, double* mu_out) {
-  if (dtype != 0 && dtype != 1) return -1;
-  if (n < 1) return -2;
-  if (!A) return -3;
-  if (lda < n) return -4;
-  if (!(emin < emax)) return -5;
-  if (nc < 1) return -7;
-  if (m0 < 1 || m0 > n) return -8;
-  if (!(tol > 0.0)) return -9;
-  if (max_iter < 1) return -10;
-  if (!(anorm > 0.0)) return -11;
-  if (!X0) return -12;
-  if (ldx0 < n) return -13;
-  if (!X) return -14;
-  if (ldx < n) return -15;
-  if (!lambda || !res || !m || !iters) return -16;
-
-  zc* Az = load_matrix(dtype, n, n, A, lda);
-  if (!all_finite(Az, (size_t)n * n)) { free(Az); return 5; }
-  zc* Xz = load_matrix(dtype, n, m0, X0, ldx0);
+/* The FEAST loop of the Appendix on the pencil (A, B) (Bz == NULL: B = I): Xz (n x m0) holds
+ * X_0 on entry and the last Ritz vectors on exit.  With B, the filter of Sec. 1 is applied to
+ * B X (rho(B^{-1}A) X = sum_j omega_j (z_j B - A)^{-1} B X + adjoint terms), Rayleigh-Ritz
+ * uses B' = Q^H B Q, and mu_k = Re(x_k^H B rho x_k). */
+static int feast_loop(int dtype, int n, const zc* Az, const zc* Bz, double emin, double emax,
+                      int nc, int m0, double tol, int max_iter, double anorm, zc* Xz,
+                      double* lambda, double* res, int* m, int* iters, double* trace,
+                      int spurious, double* mu_out) {
   zc* Qz = malloc(sizeof(zc) * (size_t)n * m0);
+  zc* BX = Bz ? malloc(sizeof(zc) * (size_t)n * m0) : NULL;
   double* mu = malloc(sizeof(double) * m0);
   factors_t f;
   memset(&f, 0, sizeof(f));
-  int st = factors_build(&f, Az, n, emin, emax, nc);
+  int st = factors_build(&f, Az, Bz, n, emin, emax, nc);
   int it = 0, prev_m = -1;
   *m = 0;
   if (st == 0) {
     st = 1;
-    filter_with_factors(&f, dtype, Xz, m0, Qz); /* step 1 of the first iteration */
+    if (Bz) matmul(0, n, m0, n, Bz, n, Xz, n, BX);
+    /* planted (9): the filter applied to X instead of B X */
+    filter_with_factors(&f, dtype, (Bz && g_fault != 9) ? BX : Xz, m0, Qz); /* step 1 */
     for (it = 1; it <= max_iter; it++) {
       int mm = 0;
-      int rst = rr_core(n, Az, Qz, m0, emin, emax, anorm, lambda, res, &mm); /* step 2 */
+      int rst = rr_core(n, Az, Bz, Qz, m0, emin, emax, anorm, lambda, res, &mm); /* step 2 */
       memcpy(Xz, Qz, sizeof(zc) * (size_t)n * m0);
       if (rst != 0) { *m = mm; st = rst; break; }
-      filter_with_factors(&f, dtype, Xz, m0, Qz); /* step 1 of the next iteration */
+      if (Bz) matmul(0, n, m0, n, Bz, n, Xz, n, BX);
+      filter_with_factors(&f, dtype, (Bz && g_fault != 9) ? BX : Xz, m0, Qz); /* next step 1 */
       double r = 0.0; /* step 3 */
       int cnt = 0;
       for (int k = 0; k < m0; k++) {
         if (!(lambda[k] > emin && lambda[k] < emax)) continue;
         if (spurious) {
+          const zc* bx = Bz ? BX : Xz;
           double d = 0.0;
           for (int i = 0; i < n; i++)
-            d += creal(conj(Xz[i + (size_t)k * n]) * Qz[i + (size_t)k * n]);
+            d += creal(conj(bx[i + (size_t)k * n]) * Qz[i + (size_t)k * n]);
           mu[k] = d;
           if (!(d > 0.5)) continue;
         }
@@ -613,19 +621,97 @@ int or_feast_solve_ex(int dtype, int n, const double* A, int lda, double emin, d
     if (it > max_iter) it = max_iter;
   }
   if (mu_out && spurious) {
+    const zc* bx = Bz ? BX : Xz;
+    if (Bz) matmul(0, n, m0, n, Bz, n, Xz, n, BX);
     for (int k = 0; k < m0; k++) {
       double d = 0.0;
-      for (int i = 0; i < n; i++) d += creal(conj(Xz[i + (size_t)k * n]) * Qz[i + (size_t)k * n]);
+      for (int i = 0; i < n; i++) d += creal(conj(bx[i + (size_t)k * n]) * Qz[i + (size_t)k * n]);
       mu_out[k] = d;
     }
   }
   *iters = it;
-  store_matrix(dtype, n, m0, Xz, X, ldx);
   factors_free(&f);
-  free(Az);
-  free(Xz);
   free(Qz);
+  free(BX);
   free(mu);
+  return st;
+}
+
+int or_feast_solve_ex(int dtype, int n, const double* A, int lda, double emin, double emax,
+                      int nc, int m0, double tol, int max_iter, double anorm, const double* X0,
+                      int ldx0, double* X, int ldx, double* lambda, double* res, int* m,
+                      int* iters, double* trace, int spurious, double* mu_out) {
+  return or_feast_solve_gen(dtype, n, A, lda, NULL, 0, emin, emax, nc, m0, tol, max_iter, anorm,
+                            X0, ldx0, X, ldx, lambda, res, m, iters, trace, spurious, mu_out);
+}
+
+int or_feast_solve_gen(int dtype, int n, const double* A, int lda, const double* B, int ldb,
+                       double emin, double emax, int nc, int m0, double tol, int max_iter,
+                       double anorm, const double* X0, int ldx0, double* X, int ldx,
+                       double* lambda, double* res, int* m, int* iters, double* trace,
+                       int spurious, double* mu_out) {
+  if (dtype != 0 && dtype != 1) return -1;
+  if (n < 1) return -2;
+  if (!A) return -3;
+  if (lda < n) return -4;
+  if (B && ldb < n) return -6;
+  if (!(emin < emax)) return -7;
+  if (nc < 1) return -9;
+  if (m0 < 1 || m0 > n) return -10;
+  if (!(tol > 0.0)) return -11;
+  if (max_iter < 1) return -12;
+  if (!(anorm > 0.0)) return -13;
+  if (!X0) return -14;
+  if (ldx0 < n) return -15;
+  if (!X) return -16;
+  if (ldx < n) return -17;
+  if (!lambda || !res || !m || !iters) return -18;
+
+  zc* Az = load_matrix(dtype, n, n, A, lda);
+  zc* Bz = B ? load_matrix(dtype, n, n, B, ldb) : NULL;
+  if (!all_finite(Az, (size_t)n * n) || (Bz && !all_finite(Bz, (size_t)n * n))) {
+    free(Az); free(Bz);
+    return 5;
+  }
+  zc* Xz = load_matrix(dtype, n, m0, X0, ldx0);
+  int st = feast_loop(dtype, n, Az, Bz, emin, emax, nc, m0, tol, max_iter, anorm, Xz, lambda,
+                      res, m, iters, trace, spurious, mu_out);
+  store_matrix(dtype, n, m0, Xz, X, ldx);
+  free(Az);
+  free(Bz);
+  free(Xz);
+  return st;
+}
+
+/* Sec. 1 eq. (contour_int_quad) on the pencil: Q = rho(B^{-1} A) X. */
+int or_filter_apply_gen(int dtype, int n, const double* A, int lda, const double* B, int ldb,
+                        double emin, double emax, int nc, const double* X, int ldx, int m0,
+                        double* Q, int ldq) {
+  if (dtype != 0 && dtype != 1) return -1;
+  if (n < 1) return -2;
+  if (!A || lda < n) return -3;
+  if (!B || ldb < n) return -5;
+  if (!(emin < emax)) return -7;
+  if (nc < 1) return -9;
+  if (!X || ldx < n) return -10;
+  if (m0 < 1 || m0 > n) return -12;
+  if (!Q || ldq < n) return -13;
+  zc* Az = load_matrix(dtype, n, n, A, lda);
+  zc* Bz = load_matrix(dtype, n, n, B, ldb);
+  zc* Xz = load_matrix(dtype, n, m0, X, ldx);
+  zc* BX = malloc(sizeof(zc) * (size_t)n * m0);
+  matmul(0, n, m0, n, Bz, n, Xz, n, BX);
+  factors_t f;
+  memset(&f, 0, sizeof(f));
+  int st = factors_build(&f, Az, Bz, n, emin, emax, nc);
+  if (st == 0) {
+    zc* Qz = malloc(sizeof(zc) * (size_t)n * m0);
+    filter_with_factors(&f, dtype, g_fault == 9 ? Xz : BX, m0, Qz);
+    store_matrix(dtype, n, m0, Qz, Q, ldq);
+    free(Qz);
+  }
+  factors_free(&f);
+  free(Az); free(Bz); free(Xz); free(BX);
   return st;
 }
 
@@ -690,7 +776,7 @@ static int rr_all(int n, const zc* A, const zc* U, int r, double anorm, zc* Y, d
                   double* res) {
   int mdummy = 0;
   memcpy(Y, U, sizeof(zc) * (size_t)n * r);
-  return rr_core(n, A, Y, r, 0.0, 0.0, anorm, lam, res, &mdummy);
+  return rr_core(n, A, NULL, Y, r, 0.0, 0.0, anorm, lam, res, &mdummy);
 }
 
 /* Selection of Sec. 2 (Method 1, also used by Method 2): every pair inside I, and if fewer
@@ -774,7 +860,7 @@ int or_xrfeast_solve(int variant, int dtype, int n, const double* A, int lda, do
   double* mu = malloc(sizeof(double) * m0);
   factors_t f;
   memset(&f, 0, sizeof(f));
-  int st = factors_build(&f, Az, n, emin, emax, nc);
+  int st = factors_build(&f, Az, NULL, n, emin, emax, nc);
   int it = 0, prev_m = -1, mm = 0, kcols = 0;
   if (st == 0 && variant == 1) { /* step 0: the Krylov-like window of filtered blocks */
     memcpy(Bw, Xs, sizeof(zc) * (size_t)n * m0);

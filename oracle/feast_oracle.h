@@ -4,7 +4,8 @@
  * standard problem A x = lambda x on an open interval I = (emin, emax), written from
  * Gavin & Polizzi, "Enhancing the Performance and Robustness of the FEAST Eigensolver"
  * (arXiv 1605.08771): the quadrature filter of Sec. 1, eq. (contour_int_quad), and the
- * FEAST algorithm of the Appendix (filter, Rayleigh-Ritz, residual test).
+ * FEAST algorithm of the Appendix (filter, Rayleigh-Ritz, residual test), the expanded-subspace
+ * variants of Sec. 2, and the generalized Hermitian-definite problem A x = lambda B x.
  *
  * Only the test suite, the smoke check and the benchmark's CPU-baseline leg may load this
  * library.  The GPU product never links, loads or calls it, and it shares no code with the
@@ -42,6 +43,14 @@ int or_feast_solve_ex(int dtype, int n, const double* A, int lda, double emin, d
                       int nc, int m0, double tol, int max_iter, double anorm, const double* X0,
                       int ldx0, double* X, int ldx, double* lambda, double* res, int* m,
                       int* iters, double* trace, int spurious, double* mu_out);
+int or_feast_solve_gen(int dtype, int n, const double* A, int lda, const double* B, int ldb,
+                       double emin, double emax, int nc, int m0, double tol, int max_iter,
+                       double anorm, const double* X0, int ldx0, double* X, int ldx,
+                       double* lambda, double* res, int* m, int* iters, double* trace,
+                       int spurious, double* mu_out);
+int or_filter_apply_gen(int dtype, int n, const double* A, int lda, const double* B, int ldb,
+                        double emin, double emax, int nc, const double* X, int ldx, int m0,
+                        double* Q, int ldq);
 int or_xrfeast_solve(int variant, int dtype, int n, const double* A, int lda, double emin,
                      double emax, int nc, int m0, int s, double tol, int max_iter, double anorm,
                      const double* X0, int ldx0, double* X, int ldx, double* lambda, double* res,

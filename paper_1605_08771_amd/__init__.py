@@ -43,7 +43,8 @@ class FeastProblem(ctypes.Structure):
                 ("emax", ctypes.c_double), ("anorm", ctypes.c_double), ("X0", ctypes.c_void_p),
                 ("X", ctypes.c_void_p), ("lambda_", ctypes.POINTER(ctypes.c_double)),
                 ("res", ctypes.POINTER(ctypes.c_double)), ("m", ctypes.POINTER(ctypes.c_int)),
-                ("iters", ctypes.POINTER(ctypes.c_int)), ("status", ctypes.POINTER(ctypes.c_int))]
+                ("iters", ctypes.POINTER(ctypes.c_int)), ("status", ctypes.POINTER(ctypes.c_int)),
+                ("mu", ctypes.POINTER(ctypes.c_double))]
 
 
 _lib = None
@@ -274,7 +275,7 @@ class Feast:
             n = _square(A)
             m0 = pr["m0"]
             X = fortran(torch.empty((n, m0), dtype=A.dtype, device=A.device))
-            lam, res = np.zeros(m0), np.zeros(m0)
+            lam, res, mu = np.zeros(m0), np.zeros(m0), np.zeros(m0)
             m, it, st = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(-999)
             X0 = pr.get("X0")
             if X0 is not None:
@@ -287,17 +288,52 @@ class Feast:
                                   X0=X0.data_ptr() if X0 is not None else None,
                                   X=X.data_ptr(), lambda_=lam.ctypes.data_as(_dp),
                                   res=res.ctypes.data_as(_dp), m=ctypes.pointer(m),
-                                  iters=ctypes.pointer(it), status=ctypes.pointer(st))
-            keep += [X, lam, res, m, it, st]
-            outs.append((X, lam, res, m, it, st))
+                                  iters=ctypes.pointer(it), status=ctypes.pointer(st),
+                                  mu=mu.ctypes.data_as(_dp))
+            keep += [X, lam, res, m, it, st, mu]
+            outs.append((X, lam, res, m, it, st, mu))
         opts = FeastOpts(n_c=n_c, m0=1, max_iter=max_iter, refine_max=refine_max, tol=tol,
                          anorm=0.0, prec=prec, seed=0, spurious=int(spurious))
         torch.cuda.synchronize()
         bad = lib().feast_solve_batched(self.h, dt, len(problems), arr, ctypes.byref(opts),
                                         nstreams)
-        results = [dict(status=st.value, X=X, lam=lam, res=res, m=m.value, iters=it.value)
-                   for (X, lam, res, m, it, st) in outs]
+        results = [dict(status=st.value, X=X, lam=lam, res=res, m=m.value, iters=it.value,
+                        mu=mu) for (X, lam, res, m, it, st, mu) in outs]
         return bad, results
+
+    def solve_slices(self, A, edges, m0, anorm=0.0, X0=None, n_c=8, tol=1e-12, max_iter=200,
+                     prec=FEAST_FP64, refine_max=0, spurious=True, nstreams=8):
+        """Eigenpairs of one matrix A in the open slices (edges[k], edges[k+1]), solved as
+        independent intervals (Sec. 1) on concurrent streams.  m0: one size for all slices or
+        one per slice; X0: None (seeded starts) or one start block per slice.  Returns
+        (count_not_ok, per-slice results, eigenvalues of all slices in ascending order).  A
+        pair counts for its slice when its Ritz value lies inside it (and mu_k > 1/2 when the
+        filter-value test is on)."""
+        import numpy as np
+        edges = [float(e) for e in edges]
+        if len(edges) < 2 or any(b <= a for a, b in zip(edges, edges[1:])):
+            raise ValueError("edges must increase")
+        k = len(edges) - 1
+        m0s = list(m0) if hasattr(m0, "__len__") else [int(m0)] * k
+        if len(m0s) != k:
+            raise ValueError("one m0 per slice")
+        probs = []
+        for i in range(k):
+            pr = dict(A=A, emin=edges[i], emax=edges[i + 1], m0=m0s[i], anorm=anorm)
+            if X0 is not None:
+                pr["X0"] = X0[i]
+            probs.append(pr)
+        bad, outs = self.solve_batched(probs, n_c=n_c, tol=tol, max_iter=max_iter, prec=prec,
+                                       refine_max=refine_max, spurious=spurious,
+                                       nstreams=nstreams)
+        found = []
+        for i, o in enumerate(outs):
+            ok = (o["lam"] > edges[i]) & (o["lam"] < edges[i + 1])
+            if spurious or prec == FEAST_FP32_IR:
+                ok &= o["mu"] > 0.5
+            o["counted"] = np.flatnonzero(ok)
+            found.append(o["lam"][ok])
+        return bad, outs, np.sort(np.concatenate(found)) if found else np.zeros(0)
 
     # ---------------------------------------------------------------- building blocks
     def gemm(self, opA, opB, A, B, C, alpha=1.0, beta=0.0, M=None, N=None, K=None):

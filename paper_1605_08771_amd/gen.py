@@ -202,6 +202,37 @@ def fig2_problem(kind="dense", m0=51, n_c=None, complex_=False, tol=1e-12, max_i
                         name=f"fig2-{kind}")
 
 
+@dataclasses.dataclass
+class PencilProblem(Problem):
+    B: object = None       # Hermitian positive definite, column-major
+    Z: object = None       # B-orthonormal eigenvectors (A Z = B Z diag(lam)), numpy only
+
+
+def pencil_problem(lam, emin, emax, m0, n_c, tol, max_iter, complex_, rng, s_range=(0.6, 1.5),
+                   name=""):
+    """A Hermitian-definite pencil with known eigenpairs: Z = U diag(s) W (U, W Haar-like
+    unitary, s uniform on s_range), B = Z^{-H} Z^{-1} = U diag(1/s^2) U^H and
+    A = Z^{-H} diag(lam) Z^{-1}, so A z_i = lam_i B z_i with z_i^H B z_j = delta_ij and A, B do
+    not commute.  Draw order: lam (given), U, s, W, X0.  Host (numpy) arrays."""
+    n = len(lam)
+    U = haar_basis(rng, n, complex_)
+    s = rng.uniform(s_range[0], s_range[1], size=n)
+    W = haar_basis(rng, n, complex_)
+    # Z^{-1} = W^H diag(1/s) U^H;  M = Z^{-H} = U diag(1/s) W
+    M = (U / s[None, :]) @ W
+    A = (M * np.asarray(lam)[None, :]) @ M.conj().T
+    A = np.asfortranarray(0.5 * (A + A.conj().T))
+    B = (U / (s * s)[None, :]) @ U.conj().T
+    B = np.asfortranarray(0.5 * (B + B.conj().T))
+    Z = np.asfortranarray((U * s[None, :]) @ W)
+    X0 = gaussian_block(rng, n, m0, complex_)
+    m_true = int(np.sum((np.asarray(lam) > emin) & (np.asarray(lam) < emax)))
+    anorm = float(np.linalg.norm(A, 2))
+    return PencilProblem(n=n, dtype="c128" if complex_ else "r64", emin=emin, emax=emax, m0=m0,
+                         n_c=n_c, tol=tol, max_iter=max_iter, lam=np.asarray(lam),
+                         m_true=m_true, anorm=anorm, A=A, U=None, X0=X0, name=name, B=B, Z=Z)
+
+
 def config1(n=500, device=None, seed_tag=1):
     """Real symmetric, lam ~ U[-1,1], I = (-0.1, 0.1), m0 = 75, n_c = 8, tol 1e-12, 20 its."""
     rng = rng_for(seed_tag)

@@ -308,3 +308,42 @@ def test_solve_batched_vs_oracle(fe, orc):
         np.testing.assert_allclose(o["lam"][sel], exact, rtol=0, atol=1e-10 * p.anorm)
         so = (r["lam"] > p.emin) & (r["lam"] < p.emax) & (r["mu"] > 0.5)
         assert sin_theta_max(r["X"][:, so], o["X"].cpu().numpy()[:, sel]) < 1e-8
+
+
+def test_slices_of_one_matrix_vs_oracle(fe, orc):
+    """Sec. 1: disjoint intervals are independent problems.  One complex Hermitian n=900 matrix
+    with (-0.3, 0.3) cut into four slices solved on concurrent streams: the union of the
+    slices' eigenvalues is the matrix's spectrum in (-0.3, 0.3), each slice matches the
+    oracle on that slice, and its eigenvectors span the exact ones of the slice."""
+    import math
+    import torch
+    edges = np.linspace(-0.3, 0.3, 5)
+    rng = gen.rng_for(90)
+    lam = rng.uniform(-1.0, 1.0, 900)
+    for _ in range(100):  # nothing within 5e-5 of a slice edge
+        near = np.min(np.abs(lam[:, None] - edges[None, :]), axis=1) < 5e-5
+        if not near.any():
+            break
+        lam[near] = rng.uniform(-1.0, 1.0, int(near.sum()))
+    p = gen.make_problem(lam, -0.3, 0.3, 8, 8, 1e-12, 200, True, rng, name="slices")
+    counts = [int(np.sum((lam > a) & (lam < b))) for a, b in zip(edges, edges[1:])]
+    m0s = [max(16, int(math.ceil(1.6 * c))) for c in counts]
+    X0s = [gen.gaussian_block(gen.rng_for([90, k]), p.n, m0s[k], True) for k in range(4)]
+    A = _dev(p.A)
+    bad, outs, found = fe.solve_slices(A, edges, m0s, anorm=p.anorm,
+                                       X0=[_dev(x) for x in X0s], tol=1e-12, nstreams=4)
+    torch.cuda.synchronize()
+    assert bad == 0, [o["status"] for o in outs]
+    exact = np.sort(lam[(lam > -0.3) & (lam < 0.3)])
+    np.testing.assert_allclose(found, exact, rtol=0, atol=1e-10 * p.anorm)
+    for k, o in enumerate(outs):
+        a, b = edges[k], edges[k + 1]
+        ref = orc.feast_solve("c128", p.A, a, b, 8, m0s[k], 1e-12, 200, p.anorm, X0s[k],
+                              spurious=True)
+        assert ref["status"] == 0 and o["m"] == ref["m"] == counts[k]
+        so = (ref["lam"] > a) & (ref["lam"] < b) & (ref["mu"] > 0.5)
+        sg = o["counted"]
+        np.testing.assert_allclose(o["lam"][sg], ref["lam"][so], rtol=0, atol=1e-10 * p.anorm)
+        X = o["X"].cpu().numpy()[:, sg]
+        ins = (lam > a) & (lam < b)
+        assert sin_theta_max(p.U[:, ins], X) < 1e-8
