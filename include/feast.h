@@ -169,6 +169,31 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
                 double emax, const feast_opts* opt, const void* X0, void* X, int ldx,
                 double* lambda, double* res, int* m, int* iters, double* trace);
 
+/* The generalized Hermitian-definite problem A x = lambda B x (Sec. 1, eq. 1), B Hermitian
+ * positive definite (real symmetric for FEAST_R64), n x n, ldb >= n, same dtype as A.
+ * The filter of eq. (contour_int_quad) becomes rho(B^{-1} A) X = sum_j omega_j (z_j B - A)^{-1}
+ * B X + the adjoint terms (the factors of z_j B - A serve both sides); Rayleigh-Ritz uses
+ * A' = Q^H A Q and B' = Q^H B Q (Cholesky-QR in the B inner product, twice).  Ritz vectors
+ * are returned with x^H B x = 1, res_k = ||A x_k - lambda_k B x_k||_2 / anorm (anorm <= 0:
+ * ||A||_2 estimated), and with opt->spurious = 1 the filter value is mu_k = Re(x_k^H B rho x_k).
+ * FP64 and the FEAST method only (opt->prec = FEAST_FP64, opt->method = FEAST_METHOD_FEAST).
+ * The factor cache is keyed by (A, B) pointers as well: call feast_invalidate if either
+ * changes in place.
+ * Argument positions: h=1 dt=2 n=3 A=4 lda=5 B=6 ldb=7 emin=8 emax=9 opt=10 X0=11 X=12
+ * ldx=13 lambda=14 res=15 m=16 iters=17; returns as feast_solve. */
+int feast_solve_gen(feast_handle h, feast_dtype dt, int n, const void* A, int lda, const void* B,
+                    int ldb, double emin, double emax, const feast_opts* opt, const void* X0,
+                    void* X, int ldx, double* lambda, double* res, int* m, int* iters,
+                    double* trace);
+
+/* Q = rho(B^{-1} A) X for the pencil (A, B) as above (prec must be FEAST_FP64).
+ * Argument positions: h=1 dt=2 n=3 A=4 lda=5 B=6 ldb=7 emin=8 emax=9 n_c=10 prec=11 X=12
+ * ldx=13 m0=14 Q=15 (!= X) ldq=16. */
+int feast_filter_apply_gen(feast_handle h, feast_dtype dt, int n, const void* A, int lda,
+                           const void* B, int ldb, double emin, double emax, int n_c,
+                           feast_precision prec, const void* X, int ldx, int m0, void* Q,
+                           int ldq);
+
 /* One problem of a batch (device arrays owned by the caller, host outputs as in feast_solve).
  * X0 may be NULL (seeded Gaussian start); X0 and X share ldx. */
 typedef struct {

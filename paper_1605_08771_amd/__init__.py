@@ -85,6 +85,10 @@ def lib():
         L.feast_solve.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int,
                                   ctypes.c_double, ctypes.c_double, ctypes.POINTER(FeastOpts),
                                   _vp, _vp, ctypes.c_int, _dp, _dp, _ip, _ip, _dp]
+        L.feast_solve_gen.argtypes = L.feast_solve.argtypes[:5] + [_vp, ctypes.c_int] + \
+            L.feast_solve.argtypes[5:]
+        L.feast_filter_apply_gen.argtypes = L.feast_filter_apply.argtypes[:5] + \
+            [_vp, ctypes.c_int] + L.feast_filter_apply.argtypes[5:]
         L.feast_get_timings.argtypes = [_vp, _dp, ctypes.c_int]
         L.feast_get_filter_values.argtypes = [_vp, _dp, ctypes.c_int]
         L.feast_solve_batched.argtypes = [_vp, ctypes.c_int, ctypes.c_int,
@@ -251,6 +255,60 @@ class Feast:
         out = dict(status=st, X=X, lam=lam, res=res, m=m.value, iters=iters.value,
                    trace=trace[: iters.value])
         if spurious or prec == FEAST_FP32_IR:
+            mu = np.zeros(m0)
+            lib().feast_get_filter_values(self.h, mu.ctypes.data_as(_dp), m0)
+            out["mu"] = mu
+        return out
+
+    def filter_apply_gen(self, A, B, X, emin, emax, n_c, Q=None):
+        """Q = rho(B^{-1} A) X for the Hermitian-definite pencil (A, B) (FP64)."""
+        import torch
+        dt = _dtype_code(A)
+        n = _square(A)
+        _need(B, "B", A.dtype, rows=n, cols=n)
+        _need(X, "X", A.dtype, rows=n)
+        lda, ldb, ldx = _ld(A, "A"), _ld(B, "B"), _ld(X, "X")
+        m0 = X.shape[1]
+        if Q is None:
+            Q = fortran(torch.empty((n, m0), dtype=X.dtype, device=X.device))
+        _need(Q, "Q", A.dtype, rows=n, cols=m0)
+        ldq = _ld(Q, "Q")
+        st = lib().feast_filter_apply_gen(self.h, dt, n, _vp(A.data_ptr()), lda,
+                                          _vp(B.data_ptr()), ldb, emin, emax, n_c, FEAST_FP64,
+                                          _vp(X.data_ptr()), ldx, m0, _vp(Q.data_ptr()), ldq)
+        return st, Q
+
+    def solve_gen(self, A, B, emin, emax, m0, n_c=8, tol=1e-12, max_iter=50, anorm=0.0,
+                  X0=None, seed=0, X=None, spurious=False):
+        """FEAST on A x = lambda B x (B Hermitian positive definite), FP64.  Ritz vectors are
+        B-normalized; res_k = ||A x_k - lambda_k B x_k|| / anorm."""
+        import numpy as np
+        import torch
+        dt = _dtype_code(A)
+        n = _square(A)
+        _need(B, "B", A.dtype, rows=n, cols=n)
+        lda, ldb = _ld(A, "A"), _ld(B, "B")
+        if X is None:
+            X = fortran(torch.empty((n, m0), dtype=A.dtype, device=A.device))
+        _need(X, "X", A.dtype, rows=n, cols=m0)
+        ldx = _ld(X, "X")
+        if X0 is not None:
+            _need(X0, "X0", A.dtype, rows=n, cols=m0)
+            if _ld(X0, "X0") != ldx:
+                raise ValueError("X0 and X must share the leading dimension")
+        opts = FeastOpts(n_c=n_c, m0=m0, max_iter=max_iter, refine_max=0, tol=tol, anorm=anorm,
+                         prec=FEAST_FP64, seed=seed, spurious=int(spurious))
+        lam, res, trace = np.zeros(m0), np.zeros(m0), np.zeros(max_iter)
+        m, iters = ctypes.c_int(0), ctypes.c_int(0)
+        st = lib().feast_solve_gen(self.h, dt, n, _vp(A.data_ptr()), lda, _vp(B.data_ptr()), ldb,
+                                   emin, emax, ctypes.byref(opts),
+                                   _vp(X0.data_ptr()) if X0 is not None else None,
+                                   _vp(X.data_ptr()), ldx, lam.ctypes.data_as(_dp),
+                                   res.ctypes.data_as(_dp), ctypes.byref(m), ctypes.byref(iters),
+                                   trace.ctypes.data_as(_dp))
+        out = dict(status=st, X=X, lam=lam, res=res, m=m.value, iters=iters.value,
+                   trace=trace[: iters.value])
+        if spurious:
             mu = np.zeros(m0)
             lib().feast_get_filter_values(self.h, mu.ctypes.data_as(_dp), m0)
             out["mu"] = mu

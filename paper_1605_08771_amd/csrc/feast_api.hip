@@ -211,16 +211,21 @@ struct feast_ctx {
   // factor cache
   bool f_valid = false;
   const void* f_A = nullptr;
-  int f_n = 0, f_lda = 0, f_dt = -1, f_nc = 0, f_prec = -1, f_np = 0, f_nbt = 0;
+  const void* f_B = nullptr;  // pencil (A, B); nullptr: B = I
+  int f_n = 0, f_lda = 0, f_ldb = 0, f_dt = -1, f_nc = 0, f_prec = -1, f_np = 0, f_nbt = 0;
   double f_emin = 0, f_emax = 0;
   std::vector<zd> z, omega;
   Buf b_fac, b_invL, b_invU, b_tri_tmp, b_luw, b_z, b_omega;
   LuWork luw;
-  // complex copy of a real A (Rayleigh-Ritz operand)
+  // complex copies of a real A and B (Rayleigh-Ritz operands)
   const void* ac_A = nullptr;
   int ac_n = 0, ac_lda = 0;
   bool ac_valid = false;
   Buf b_Ac;
+  const void* bc_B = nullptr;
+  int bc_n = 0, bc_ldb = 0;
+  bool bc_valid = false;
+  Buf b_Bc, b_BQ, b_BX, b_BXf;
   // right-hand sides / solutions
   Buf b_B, b_Z, b_Xc, b_Qc, b_X0c;
   // Rayleigh-Ritz
@@ -253,9 +258,10 @@ int pick_nbt(int n) {
 
 // Factorizations of z_j I - A for all nodes (cached).
 int ensure_factors(feast_ctx* h, int dt, int n, const void* A, int lda, double emin, double emax,
-                   int nc, int prec) {
+                   int nc, int prec, const void* B = nullptr, int ldb = 0) {
   if (h->f_valid && h->f_A == A && h->f_n == n && h->f_lda == lda && h->f_dt == dt &&
-      h->f_nc == nc && h->f_prec == prec && h->f_emin == emin && h->f_emax == emax)
+      h->f_nc == nc && h->f_prec == prec && h->f_emin == emin && h->f_emax == emax &&
+      h->f_B == B && h->f_ldb == ldb)
     return 0;
   h->f_valid = false;
   hipStream_t s = h->stream;
@@ -284,7 +290,7 @@ int ensure_factors(feast_ctx* h, int dt, int n, const void* A, int lda, double e
   int st = 0;
   if (prec == FEAST_FP64) {
     zd* F = h->b_fac.get<zd>((size_t)nc * np * np);
-    shift_matrices(s, A, lda, dt == FEAST_R64, n, np, zdev, nc, F);
+    shift_matrices(s, A, lda, dt == FEAST_R64, n, np, zdev, nc, F, B, ldb);
     if (nonfinite_check(s, F, np, np, np, h->luw.flag)) return FEAST_NONFINITE;
     {
       ScopedProf sp(h->prof, K_LU);
@@ -303,7 +309,7 @@ int ensure_factors(feast_ctx* h, int dt, int n, const void* A, int lda, double e
     }
   } else {
     zf* F = h->b_fac.get<zf>((size_t)nc * np * np);
-    shift_matrices_f32(s, A, lda, dt == FEAST_R64, n, np, zdev, nc, F);
+    shift_matrices_f32(s, A, lda, dt == FEAST_R64, n, np, zdev, nc, F, B, ldb);
     {
       ScopedProf sp(h->prof, K_LU);
       lu_factor_f32(s, F, np, nc, h->luw);
@@ -325,6 +331,8 @@ int ensure_factors(feast_ctx* h, int dt, int n, const void* A, int lda, double e
   if (st) return st;
   h->f_valid = true;
   h->f_A = A;
+  h->f_B = B;
+  h->f_ldb = ldb;
   h->f_n = n;
   h->f_lda = lda;
   h->f_dt = dt;
@@ -354,6 +362,30 @@ const zd* complex_A(feast_ctx* h, int dt, int n, const void* A, int lda, long* l
   *ld_out = n;
   return (const zd*)h->b_Ac.p;
 }
+
+// Complex n x n copy of a real B (FEAST_R64), or B itself.
+const zd* complex_B(feast_ctx* h, int dt, int n, const void* B, int ldb, long* ld_out) {
+  if (dt == FEAST_C128) {
+    *ld_out = ldb;
+    return (const zd*)B;
+  }
+  if (!(h->bc_valid && h->bc_B == B && h->bc_n == n && h->bc_ldb == ldb)) {
+    zd* Bc = h->b_Bc.get<zd>((size_t)n * n);
+    real_to_complex(h->stream, (const double*)B, ldb, Bc, n, n, n);
+    h->bc_valid = true;
+    h->bc_B = B;
+    h->bc_n = n;
+    h->bc_ldb = ldb;
+  }
+  *ld_out = n;
+  return (const zd*)h->b_Bc.p;
+}
+
+// The pencil's B for Rayleigh-Ritz and the filter's right-hand side (nullptr: B = I).
+struct PencilB {
+  const zd* B = nullptr;
+  long ld = 0;
+};
 
 // Ritz information of the block handed to the filter (FEAST loop, iteration >= 2): X are Ritz
 // vectors with values lam (device) and FP64 residual R = A X - X diag(lam) (n x m0, ld n).
@@ -455,19 +487,32 @@ int filter_core(feast_ctx* h, int dt, int n, int m0, const zd* X, long ldx, zd* 
 
 // Q <- Q R^{-1} with G = Q^H Q = R^H R; Q1 (nq x m0 zero-padded rows) -> Q2.
 // Returns 0, 1 on Cholesky breakdown.
-int cholqr_pass(feast_ctx* h, int n, int m0, const zd* Q1, zd* Q2, double shift_rel) {
+// G = Q1^H Q1, or Q1^H (B Q1) for a pencil (split-K products, Hermitian reduction).
+void gram_matrix(feast_ctx* h, int n, int m0, const zd* Q1, const PencilB& pb, zd* G) {
   hipStream_t s = h->stream;
   const int nsplit = std::max(1, std::min(32, n / 256));
   const int kc = (n + nsplit - 1) / nsplit;
   zd* part = h->b_part.get<zd>((size_t)nsplit * m0 * m0);
-  zd* G = h->b_G.get<zd>((size_t)m0 * m0);
-  int* flag = h->b_flag.get<int>(64);
+  const zd* R = Q1;
+  if (pb.B) {
+    zd* BQ = h->b_BQ.get<zd>((size_t)n * m0);
+    zgemm(s, OP_N, OP_N, n, m0, n, zmake(1, 0), pb.B, pb.ld, Q1, n, zmake(0, 0), BQ, n);
+    R = BQ;
+  }
   Batch b;
   b.n1 = nsplit;
   b.splitk = kc;
   b.sC1 = (long)m0 * m0;
-  zgemm(s, OP_C, OP_N, m0, m0, n, zmake(1, 0), Q1, n, Q1, n, zmake(0, 0), part, m0, b);
+  zgemm(s, OP_C, OP_N, m0, m0, n, zmake(1, 0), Q1, n, R, n, zmake(0, 0), part, m0, b);
   reduce_partials_hermitian(s, part, nsplit, m0, G, m0);
+}
+
+int cholqr_pass(feast_ctx* h, int n, int m0, const zd* Q1, zd* Q2, double shift_rel,
+                const PencilB& pb) {
+  hipStream_t s = h->stream;
+  zd* G = h->b_G.get<zd>((size_t)m0 * m0);
+  int* flag = h->b_flag.get<int>(64);
+  gram_matrix(h, n, m0, Q1, pb, G);
   if (shift_rel > 0) {
     // sigma = shift_rel * trace(G) (trace bounds ||G||_2)
     double* dg = h->b_diag.get<double>(m0);
@@ -496,7 +541,7 @@ int cholqr_pass(feast_ctx* h, int n, int m0, const zd* Q1, zd* Q2, double shift_
 // Rayleigh-Ritz on Qin (n x m0 complex, ldq); Ritz vectors written back to Qin.
 int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m0, double emin,
             double emax, double anorm, double* lam_h, double* res_h, int* m_out,
-            zd* Reig = nullptr, bool quant = false) {
+            zd* Reig = nullptr, bool quant = false, const PencilB& pb = PencilB()) {
   hipStream_t s = h->stream;
   ScopedProf sp(h->prof, K_RR);
   hipEvent_t e0 = h->timer.mark(s);
@@ -511,16 +556,8 @@ int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m
   // Cholesky-QR twice; shifted Cholesky-QR3 when the first Cholesky breaks down.
   {
     // column norms from the first Gram matrix decide exact rank deficiency
-    const int nsplit = std::max(1, std::min(32, n / 256));
-    const int kc = (n + nsplit - 1) / nsplit;
-    zd* part = h->b_part.get<zd>((size_t)nsplit * m0 * m0);
     zd* G = h->b_G.get<zd>((size_t)m0 * m0);
-    Batch b;
-    b.n1 = nsplit;
-    b.splitk = kc;
-    b.sC1 = (long)m0 * m0;
-    zgemm(s, OP_C, OP_N, m0, m0, n, zmake(1, 0), Q1, n, Q1, n, zmake(0, 0), part, m0, b);
-    reduce_partials_hermitian(s, part, nsplit, m0, G, m0);
+    gram_matrix(h, n, m0, Q1, pb, G);
     double* dg = h->b_diag.get<double>(m0);
     diag_real(s, G, m0, m0, dg);
     std::vector<double> hd(m0);
@@ -534,17 +571,17 @@ int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m
     }
     if (!(mx > 0) || !(mn > 1e-26 * mx)) return FEAST_B_NOT_SPD;
   }
-  if (cholqr_pass(h, n, m0, Q1, Q2, 0.0) == 0) {
-    if (cholqr_pass(h, n, m0, Q2, Q1, 0.0) != 0) return FEAST_B_NOT_SPD;
+  if (cholqr_pass(h, n, m0, Q1, Q2, 0.0, pb) == 0) {
+    if (cholqr_pass(h, n, m0, Q2, Q1, 0.0, pb) != 0) return FEAST_B_NOT_SPD;
   } else {
     const double u = 1.1102230246251565e-16;
     const double shift = 11.0 * ((double)m0 * n + (double)m0 * (m0 + 1)) * u;
-    if (cholqr_pass(h, n, m0, Q1, Q2, shift) != 0) return FEAST_B_NOT_SPD;
-    if (cholqr_pass(h, n, m0, Q2, Q1, 0.0) != 0) return FEAST_B_NOT_SPD;
-    if (cholqr_pass(h, n, m0, Q1, Q2, 0.0) != 0) return FEAST_B_NOT_SPD;
+    if (cholqr_pass(h, n, m0, Q1, Q2, shift, pb) != 0) return FEAST_B_NOT_SPD;
+    if (cholqr_pass(h, n, m0, Q2, Q1, 0.0, pb) != 0) return FEAST_B_NOT_SPD;
+    if (cholqr_pass(h, n, m0, Q1, Q2, 0.0, pb) != 0) return FEAST_B_NOT_SPD;
     std::swap(Q1, Q2);
   }
-  // Q1 orthonormal.  A' = Q^H (A Q).
+  // Q1 orthonormal (B-orthonormal for a pencil).  A' = Q^H (A Q).
   zd* AQ = h->b_AQ.get<zd>((size_t)n * m0);
   zgemm(s, OP_N, OP_N, n, m0, n, zmake(1, 0), A, lda, Q1, n, zmake(0, 0), AQ, n);
   const int nsplit = std::max(1, std::min(32, n / 256));
@@ -576,9 +613,15 @@ int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m
   zd* AX = h->b_AX.get<zd>((size_t)n * m0);
   zgemm(s, OP_N, OP_N, n, m0, m0, zmake(1, 0), Q1, n, W, m0, zmake(0, 0), Q2, n);   // X
   zgemm(s, OP_N, OP_N, n, m0, m0, zmake(1, 0), AQ, n, W, m0, zmake(0, 0), AX, n);   // A X
+  const zd* BX = Q2;  // B X (X itself when B = I)
+  if (pb.B) {
+    zd* bx = h->b_BX.get<zd>((size_t)n * m0);
+    zgemm(s, OP_N, OP_N, n, m0, n, zmake(1, 0), pb.B, pb.ld, Q2, n, zmake(0, 0), bx, n);
+    BX = bx;
+  }
   double* res = h->b_res.get<double>(m0);
-  residual_norms(s, AX, n, Q2, n, lam, n, m0, anorm, res);
-  if (Reig) ritz_residual(s, AX, n, Q2, n, lam, n, m0, Reig);
+  residual_norms(s, AX, n, BX, n, lam, n, m0, anorm, res);
+  if (Reig) ritz_residual(s, AX, n, BX, n, lam, n, m0, Reig);
   copy_matrix(s, Q2, n, Qin, ldq, n, m0);
   FEAST_HIP(hipMemcpyAsync(lam_h, lam, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
   FEAST_HIP(hipMemcpyAsync(res_h, res, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
@@ -605,7 +648,7 @@ void finish_timing(feast_ctx* h) {
 // and the start block Xw (n x m0, from X0 or seeded Gaussian).  Returns 0 or a status.
 int solve_setup(feast_ctx* h, feast_dtype dt, int n, const void* A, int lda, double emin,
                 double emax, const feast_opts* opt, const void* X0, int ldx, const zd** Ac_out,
-                long* ldac, double* anorm_out, zd* Xw) {
+                long* ldac, double* anorm_out, zd* Xw, const void* B = nullptr, int ldb = 0) {
   hipStream_t s = h->stream;
   const int m0 = opt->m0;
   const zd* Ac = complex_A(h, dt, n, A, lda, ldac);
@@ -618,7 +661,7 @@ int solve_setup(feast_ctx* h, feast_dtype dt, int n, const void* A, int lda, dou
     if (!(anorm > 0)) anorm = 1.0;
   }
   *anorm_out = anorm;
-  int st = ensure_factors(h, dt, n, A, lda, emin, emax, opt->n_c, opt->prec);
+  int st = ensure_factors(h, dt, n, A, lda, emin, emax, opt->n_c, opt->prec, B, ldb);
   if (st) return st;
   if (X0) {
     if (dt == FEAST_R64) real_to_complex(s, (const double*)X0, ldx, Xw, n, n, m0);
@@ -1044,31 +1087,16 @@ int feast_rayleigh_ritz(feast_handle h, feast_dtype dt, int n, const void* A, in
   }
 }
 
-int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, double emin,
-                double emax, const feast_opts* opt, const void* X0, void* X, int ldx,
-                double* lambda, double* res, int* m, int* iters, double* trace) {
-  if (!h) return -1;
-  if (dt != FEAST_R64 && dt != FEAST_C128) return -2;
-  if (n < 1) return -3;
-  if (!A) return -4;
-  if (lda < n) return -5;
-  if (!std::isfinite(emin)) return -6;
-  if (!std::isfinite(emax) || !(emin < emax)) return -7;
-  if (!opt || opt->n_c < 1 || opt->n_c > 128 || opt->m0 < 1 || opt->m0 > n ||
-      opt->max_iter < 1 || !(opt->tol > 0) ||
-      (opt->prec != FEAST_FP64 && opt->prec != FEAST_FP32_IR) ||
-      (opt->prec == FEAST_FP32_IR && opt->refine_max < 0) ||
-      (opt->method != FEAST_METHOD_FEAST && opt->method != FEAST_METHOD_XFEAST &&
-       opt->method != FEAST_METHOD_RFEAST) ||
-      (opt->method != FEAST_METHOD_FEAST &&
-       (opt->expand < 1 || (long)opt->expand * opt->m0 > n)))
-    return -8;
-  if (!X) return -10;
-  if (ldx < n) return -11;
-  if (!lambda) return -12;
-  if (!res) return -13;
-  if (!m) return -14;
-  if (!iters) return -15;
+}  // extern "C"
+
+namespace {
+// The FEAST loop of the Appendix on A (B == nullptr) or on the pencil (A, B): the filter is
+// applied to B X (rho(B^{-1} A) X = sum_j omega_j (z_j B - A)^{-1} B X + adjoint terms),
+// Rayleigh-Ritz B-orthonormalizes, residuals are ||A x - lambda B x||, and the filter value
+// of a Ritz vector is mu_k = Re(x_k^H B rho x_k).  Arguments checked by the callers.
+int solve_impl(feast_handle h, feast_dtype dt, int n, const void* A, int lda, const void* B,
+               int ldb, double emin, double emax, const feast_opts* opt, const void* X0, void* X,
+               int ldx, double* lambda, double* res, int* m, int* iters, double* trace) {
   const int m0 = opt->m0;
   try {
     hipStream_t s = h->stream;
@@ -1078,7 +1106,8 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
     const zd* Ac = nullptr;
     double anorm = 0;
     zd* Xw = h->b_X0c.get<zd>((size_t)n * m0);
-    int st = solve_setup(h, dt, n, A, lda, emin, emax, opt, X0, ldx, &Ac, &ldac, &anorm, Xw);
+    int st = solve_setup(h, dt, n, A, lda, emin, emax, opt, X0, ldx, &Ac, &ldac, &anorm, Xw,
+                         B, ldb);
     if (st) {
       FEAST_HIP(hipStreamSynchronize(s));
       finish_timing(h);
@@ -1090,6 +1119,15 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
       return xr_solve(h, dt, n, Ac, ldac, anorm, emin, emax, opt, Xw, X, ldx, lambda, res, m,
                       iters, trace, t0);
     zd* Qf = h->b_Qc.get<zd>((size_t)n * m0);
+    PencilB pb;
+    if (B) pb.B = complex_B(h, dt, n, B, ldb, &pb.ld);
+    zd* BXf = B ? h->b_BXf.get<zd>((size_t)n * m0) : nullptr;
+    // the filter's right-hand side for the block Xc: Xc itself, or B Xc for a pencil
+    auto rhs = [&](const zd* Xc) -> const zd* {
+      if (!B) return Xc;
+      zgemm(s, OP_N, OP_N, n, m0, n, zmake(1, 0), pb.B, pb.ld, Xc, n, zmake(0, 0), BXf, n);
+      return BXf;
+    };
     st = FEAST_NOT_CONVERGED;
     int it = 0, prev_m = -1, mm = 0;
     // FP32 factors leave the filtered block's damped directions (|rho| far below the FP32
@@ -1100,7 +1138,7 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
     const bool mixed = opt->prec == FEAST_FP32_IR;
     zd* Reig = mixed ? h->b_Reig.get<zd>((size_t)n * m0) : nullptr;
     RitzInfo ri{Reig, nullptr};
-    int fs = filter_core(h, dt, n, m0, Xw, n, Qf, n, Ac, ldac, nullptr,
+    int fs = filter_core(h, dt, n, m0, rhs(Xw), n, Qf, n, Ac, ldac, nullptr,
                          opt->refine_max);  // step 1 of the first iteration
     if (fs) {
       st = fs;
@@ -1108,7 +1146,7 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
     }
     for (it = 1; fs == 0 && it <= opt->max_iter; ++it) {
       int rs = rr_core(h, Ac, ldac, n, Qf, n, m0, emin, emax, anorm, lambda, res, &mm,
-                       Reig);  // step 2
+                       Reig, false, pb);  // step 2
       std::swap(Xw, Qf);  // Ritz vectors become the next block
       ri.lam = (const double*)h->b_lam.p;
       if (rs) {
@@ -1117,13 +1155,14 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
         break;
       }
       if (spur) {  // the next step 1 gives mu_k = Re(x_k^H rho(A) x_k)
-        fs = filter_core(h, dt, n, m0, Xw, n, Qf, n, Ac, ldac, mixed ? &ri : nullptr);
+        const zd* bx = rhs(Xw);
+        fs = filter_core(h, dt, n, m0, bx, n, Qf, n, Ac, ldac, mixed ? &ri : nullptr);
         if (fs) {
           st = fs;
           break;
         }
         double* dmu = h->b_mu.get<double>(m0);
-        coldot_re(s, Xw, n, Qf, n, n, m0, dmu);
+        coldot_re(s, bx, n, Qf, n, n, m0, dmu);
         FEAST_HIP(hipMemcpyAsync(h->mu.data(), dmu, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
         FEAST_HIP(hipStreamSynchronize(s));
       }
@@ -1152,7 +1191,7 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
       }
       prev_m = mm;
       if (!spur && it < opt->max_iter) {
-        fs = filter_core(h, dt, n, m0, Xw, n, Qf, n, Ac, ldac,
+        fs = filter_core(h, dt, n, m0, rhs(Xw), n, Qf, n, Ac, ldac,
                          mixed ? &ri : nullptr);  // step 1 of the next iteration
         if (fs) {
           st = fs;
@@ -1165,6 +1204,122 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
     *m = mm;
     if (dt == FEAST_R64) complex_to_real(s, Xw, n, (double*)X, ldx, n, m0);
     else copy_matrix(s, Xw, n, (zd*)X, ldx, n, m0);
+    hipEvent_t t1 = h->timer.mark(s);
+    h->timer.add(t0, t1, P_TOTAL);
+    FEAST_HIP(hipStreamSynchronize(s));
+    finish_timing(h);
+    return st;
+  } catch (const HipError& e) {
+    return fail_hip(h, e);
+  } catch (const std::bad_alloc&) {
+    return FEAST_ERR_ALLOC;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, double emin,
+                double emax, const feast_opts* opt, const void* X0, void* X, int ldx,
+                double* lambda, double* res, int* m, int* iters, double* trace) {
+  if (!h) return -1;
+  if (dt != FEAST_R64 && dt != FEAST_C128) return -2;
+  if (n < 1) return -3;
+  if (!A) return -4;
+  if (lda < n) return -5;
+  if (!std::isfinite(emin)) return -6;
+  if (!std::isfinite(emax) || !(emin < emax)) return -7;
+  if (!opt || opt->n_c < 1 || opt->n_c > 128 || opt->m0 < 1 || opt->m0 > n ||
+      opt->max_iter < 1 || !(opt->tol > 0) ||
+      (opt->prec != FEAST_FP64 && opt->prec != FEAST_FP32_IR) ||
+      (opt->prec == FEAST_FP32_IR && opt->refine_max < 0) ||
+      (opt->method != FEAST_METHOD_FEAST && opt->method != FEAST_METHOD_XFEAST &&
+       opt->method != FEAST_METHOD_RFEAST) ||
+      (opt->method != FEAST_METHOD_FEAST &&
+       (opt->expand < 1 || (long)opt->expand * opt->m0 > n)))
+    return -8;
+  if (!X) return -10;
+  if (ldx < n) return -11;
+  if (!lambda) return -12;
+  if (!res) return -13;
+  if (!m) return -14;
+  if (!iters) return -15;
+  return solve_impl(h, dt, n, A, lda, nullptr, 0, emin, emax, opt, X0, X, ldx, lambda, res, m,
+                    iters, trace);
+}
+
+int feast_solve_gen(feast_handle h, feast_dtype dt, int n, const void* A, int lda, const void* B,
+                    int ldb, double emin, double emax, const feast_opts* opt, const void* X0,
+                    void* X, int ldx, double* lambda, double* res, int* m, int* iters,
+                    double* trace) {
+  if (!h) return -1;
+  if (dt != FEAST_R64 && dt != FEAST_C128) return -2;
+  if (n < 1) return -3;
+  if (!A) return -4;
+  if (lda < n) return -5;
+  if (!B) return -6;
+  if (ldb < n) return -7;
+  if (!std::isfinite(emin)) return -8;
+  if (!std::isfinite(emax) || !(emin < emax)) return -9;
+  if (!opt || opt->n_c < 1 || opt->n_c > 128 || opt->m0 < 1 || opt->m0 > n ||
+      opt->max_iter < 1 || !(opt->tol > 0) || opt->prec != FEAST_FP64 ||
+      opt->method != FEAST_METHOD_FEAST)
+    return -10;
+  if (!X) return -12;
+  if (ldx < n) return -13;
+  if (!lambda) return -14;
+  if (!res) return -15;
+  if (!m) return -16;
+  if (!iters) return -17;
+  return solve_impl(h, dt, n, A, lda, B, ldb, emin, emax, opt, X0, X, ldx, lambda, res, m, iters,
+                    trace);
+}
+
+int feast_filter_apply_gen(feast_handle h, feast_dtype dt, int n, const void* A, int lda,
+                           const void* B, int ldb, double emin, double emax, int n_c,
+                           feast_precision prec, const void* X, int ldx, int m0, void* Q,
+                           int ldq) {
+  if (!h) return -1;
+  if (dt != FEAST_R64 && dt != FEAST_C128) return -2;
+  if (n < 1) return -3;
+  if (!A) return -4;
+  if (lda < n) return -5;
+  if (!B) return -6;
+  if (ldb < n) return -7;
+  if (!std::isfinite(emin)) return -8;
+  if (!std::isfinite(emax) || !(emin < emax)) return -9;
+  if (n_c < 1 || n_c > 128) return -10;
+  if (prec != FEAST_FP64) return -11;
+  if (!X) return -12;
+  if (ldx < n) return -13;
+  if (m0 < 1 || m0 > n) return -14;
+  if (!Q || Q == X) return -15;
+  if (ldq < n) return -16;
+  try {
+    hipStream_t s = h->stream;
+    h->timer.clear();
+    hipEvent_t t0 = h->timer.mark(s);
+    int st = ensure_factors(h, dt, n, A, lda, emin, emax, n_c, prec, B, ldb);
+    if (st) {
+      finish_timing(h);
+      return st;
+    }
+    const zd* Xc = (const zd*)X;
+    long ldxc = ldx;
+    if (dt == FEAST_R64) {
+      zd* xb = h->b_Xc.get<zd>((size_t)n * m0);
+      real_to_complex(s, (const double*)X, ldx, xb, n, n, m0);
+      Xc = xb;
+      ldxc = n;
+    }
+    long ldbc = 0;
+    const zd* Bc = complex_B(h, dt, n, B, ldb, &ldbc);
+    zd* BX = h->b_BXf.get<zd>((size_t)n * m0);
+    zgemm(s, OP_N, OP_N, n, m0, n, zmake(1, 0), Bc, ldbc, Xc, ldxc, zmake(0, 0), BX, n);
+    zd* Qc = (dt == FEAST_R64) ? h->b_Qc.get<zd>((size_t)n * m0) : (zd*)Q;
+    long ldqc = (dt == FEAST_R64) ? n : ldq;
+    st = filter_core(h, dt, n, m0, BX, n, Qc, ldqc);
+    if (st == 0 && dt == FEAST_R64) complex_to_real(s, Qc, n, (double*)Q, ldq, n, m0);
     hipEvent_t t1 = h->timer.mark(s);
     h->timer.add(t0, t1, P_TOTAL);
     FEAST_HIP(hipStreamSynchronize(s));

@@ -37,12 +37,13 @@ void cgemm_pair(hipStream_t s, int opA0, int opA1, int opB, int M, int N, int K,
                 zf beta, zf* const C[2], const long ldc[2], const Batch& bt = Batch());
 
 // ---- LU (lu.hip) ---------------------------------------------------------------------
-// Shifted copies M_j = z_j I - A (j < nc) of a real (is_real) or complex n x n matrix into
-// np x np factor storage (ld = np, batch stride np*np); rows/cols n..np-1 set to identity.
+// Shifted copies M_j = z_j B - A (j < nc; B = I when B == nullptr) of real (is_real) or
+// complex n x n matrices into np x np factor storage (ld = np, batch stride np*np);
+// rows/cols n..np-1 set to identity.
 void shift_matrices(hipStream_t s, const void* A, long lda, int is_real, int n, int np,
-                    const zd* z_dev, int nc, zd* M);
+                    const zd* z_dev, int nc, zd* M, const void* B = nullptr, long ldb = 0);
 void shift_matrices_f32(hipStream_t s, const void* A, long lda, int is_real, int n, int np,
-                        const zd* z_dev, int nc, zf* M);
+                        const zd* z_dev, int nc, zf* M, const void* B = nullptr, long ldb = 0);
 
 // Workspace for the batched LU with partial pivoting.
 struct LuWork {

@@ -55,33 +55,37 @@ __device__ inline v2 crecip(v2 a) {  // 1 / a with Smith scaling
   return r;
 }
 
+// M_j = z_j B - A (B == nullptr: B = I); A and B real (is_real) or complex.
 template <typename T>
-__global__ void shift_kernel(const void* __restrict__ A, long lda, int is_real, int n, int np,
-                             const zd* __restrict__ z, int nc, typename V2<T>::t* __restrict__ M) {
+__global__ void shift_kernel(const void* __restrict__ A, long lda, const void* __restrict__ B,
+                             long ldb, int is_real, int n, int np, const zd* __restrict__ z,
+                             int nc, typename V2<T>::t* __restrict__ M) {
   typedef typename V2<T>::t v2;
   long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   long total = (long)np * np;
   if (idx >= total) return;
   int i = (int)(idx % np), c = (int)(idx / np);
-  double ar = 0, ai = 0;
+  double ar = 0, ai = 0, br = (i == c) ? 1.0 : 0.0, bi = 0;
   bool inside = (i < n && c < n);
   if (inside) {
     if (is_real) {
       ar = ((const double*)A)[i + (long)c * lda];
+      if (B) br = ((const double*)B)[i + (long)c * ldb];
     } else {
       zd a = ((const zd*)A)[i + (long)c * lda];
       ar = a.x;
       ai = a.y;
+      if (B) {
+        zd b = ((const zd*)B)[i + (long)c * ldb];
+        br = b.x;
+        bi = b.y;
+      }
     }
   }
   for (int j = 0; j < nc; ++j) {
     v2 out;
     if (inside) {
-      double re = -ar, im = -ai;
-      if (i == c) {
-        re += z[j].x;
-        im += z[j].y;
-      }
+      double re = z[j].x * br - z[j].y * bi - ar, im = z[j].x * bi + z[j].y * br - ai;
       out.x = (T)re;
       out.y = (T)im;
     } else {
@@ -465,17 +469,17 @@ void lu_work_carve(LuWork& w, void* base, int np, int nc) {
 }
 
 void shift_matrices(hipStream_t s, const void* A, long lda, int is_real, int n, int np,
-                    const zd* z_dev, int nc, zd* M) {
+                    const zd* z_dev, int nc, zd* M, const void* B, long ldb) {
   long tot = (long)np * np;
-  hipLaunchKernelGGL((shift_kernel<double>), dim3((tot + 255) / 256), dim3(256), 0, s, A, lda,
-                     is_real, n, np, z_dev, nc, M);
+  hipLaunchKernelGGL((shift_kernel<double>), dim3((tot + 255) / 256), dim3(256), 0, s, A, lda, B,
+                     ldb, is_real, n, np, z_dev, nc, M);
   FEAST_LAUNCH_CHECK();
 }
 void shift_matrices_f32(hipStream_t s, const void* A, long lda, int is_real, int n, int np,
-                        const zd* z_dev, int nc, zf* M) {
+                        const zd* z_dev, int nc, zf* M, const void* B, long ldb) {
   long tot = (long)np * np;
-  hipLaunchKernelGGL((shift_kernel<float>), dim3((tot + 255) / 256), dim3(256), 0, s, A, lda,
-                     is_real, n, np, z_dev, nc, M);
+  hipLaunchKernelGGL((shift_kernel<float>), dim3((tot + 255) / 256), dim3(256), 0, s, A, lda, B,
+                     ldb, is_real, n, np, z_dev, nc, M);
   FEAST_LAUNCH_CHECK();
 }
 

@@ -192,3 +192,52 @@ def test_binding_refuses_mismatched_tensors():
     fm._need(torch.zeros(4, 3, dtype=torch.complex128), "X", torch.complex128, rows=4, cols=3)
     with pytest.raises(TypeError):
         fm._dtype_code(torch.zeros(2, 2, dtype=torch.float32))
+
+
+def test_pencil_entry_points_argument_checks():
+    """feast_solve_gen / feast_filter_apply_gen reject bad arguments before any launch."""
+    L = fm.lib()
+    lam = (ctypes.c_double * 8)()
+    res = (ctypes.c_double * 8)()
+    m = ctypes.c_int()
+    it = ctypes.c_int()
+    dp = ctypes.POINTER(ctypes.c_double)
+    good = fm.FeastOpts(n_c=8, m0=4, max_iter=10, refine_max=0, tol=1e-12, anorm=1.0, prec=0,
+                        seed=1)
+
+    def solve(opts=good, **kw):
+        a = dict(h=BAD, dt=1, n=10, A=DEV, lda=10, B=DEV, ldb=10, emin=-1.0, emax=1.0, X0=None,
+                 X=ctypes.c_void_p(0x3000), ldx=10)
+        a.update(kw)
+        return L.feast_solve_gen(a["h"], a["dt"], a["n"], a["A"], a["lda"], a["B"], a["ldb"],
+                                 a["emin"], a["emax"],
+                                 ctypes.byref(opts) if opts is not None else None, a["X0"],
+                                 a["X"], a["ldx"], ctypes.cast(lam, dp), ctypes.cast(res, dp),
+                                 ctypes.byref(m), ctypes.byref(it), None)
+
+    assert solve(h=None) == -1
+    assert solve(dt=3) == -2
+    assert solve(B=None) == -6
+    assert solve(ldb=9) == -7
+    assert solve(emax=-3.0) == -9
+    assert solve(opts=None) == -10
+    for bad in (dict(prec=1), dict(method=1, expand=1), dict(m0=11)):
+        o = fm.FeastOpts(n_c=8, m0=4, max_iter=10, refine_max=0, tol=1e-12, anorm=1.0, prec=0,
+                         seed=1)
+        for k, v in bad.items():
+            setattr(o, k, v)
+        assert solve(opts=o) == -10, bad
+    assert solve(X=None) == -12
+
+    def filt(**kw):
+        a = dict(h=BAD, dt=1, n=10, A=DEV, lda=10, B=DEV, ldb=10, emin=-1.0, emax=1.0, nc=8,
+                 prec=0, X=DEV, ldx=10, m0=4, Q=ctypes.c_void_p(0x3000), ldq=10)
+        a.update(kw)
+        return L.feast_filter_apply_gen(a["h"], a["dt"], a["n"], a["A"], a["lda"], a["B"],
+                                        a["ldb"], a["emin"], a["emax"], a["nc"], a["prec"],
+                                        a["X"], a["ldx"], a["m0"], a["Q"], a["ldq"])
+
+    assert filt(B=None) == -6
+    assert filt(prec=1) == -11
+    assert filt(Q=DEV) == -15
+    assert filt(ldq=3) == -16
