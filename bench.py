@@ -166,11 +166,6 @@ def bench_batched(args, dev):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t1
     f.close()
-    traffic = None
-    if (args.workload == "c2" and p.n == 8192 and prec == fm.FEAST_FP64
-            and kernel_sources_hash() == SWEEP_TRAFFIC["sources"]):
-        traffic = SWEEP_TRAFFIC["bytes_per_launch"]
-
     line = {
         "metric": METRIC, "value": round(total / args.steps, 4), "unit": "s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
@@ -355,6 +350,11 @@ def main():
         z, _ = oracle.contour(p.emin, p.emax, p.n_c)
         cpu = cpu_baseline(p, int(np.median(iters)), z)
         log(f"[bench] cpu baseline: {cpu}")
+
+    traffic = None
+    if (args.workload == "c2" and p.n == 8192 and prec == fm.FEAST_FP64
+            and kernel_sources_hash() == SWEEP_TRAFFIC["sources"]):
+        traffic = SWEEP_TRAFFIC["bytes_per_launch"]
 
     line = {
         "metric": METRIC,

@@ -599,7 +599,7 @@ int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m
   const int mp = quant ? jacobi_order_quantized(m0) : jacobi_order(m0);
   double* d = h->b_d.get<double>(mp);
   zd* V = h->b_V.get<zd>((size_t)mp * mp);
-  zd* jw = h->b_jac.get<zd>(3 * (size_t)mp * mp);
+  zd* jw = h->b_jac.get<zd>(jacobi_work(mp));
   int* dflag = h->b_flag.get<int>(64);
   hipEvent_t ej = h->prof.on ? h->prof.pool.take() : nullptr;
   if (ej) FEAST_HIP(hipEventRecord(ej, s));
@@ -702,7 +702,7 @@ int gram_orthonormal(feast_ctx* h, int n, int k, zd* B, zd* U) {
   const int mp = jacobi_order_quantized(k);
   double* d = h->b_d.get<double>(mp);
   zd* V = h->b_V.get<zd>((size_t)mp * mp);
-  zd* jw = h->b_jac.get<zd>(3 * (size_t)mp * mp);
+  zd* jw = h->b_jac.get<zd>(jacobi_work(mp));
   int* dflag = h->b_flag.get<int>(64);
   hipEvent_t ej = h->prof.on ? h->prof.pool.take() : nullptr;
   if (ej) FEAST_HIP(hipEventRecord(ej, s));
@@ -773,7 +773,7 @@ int xr_solve(feast_ctx* h, feast_dtype dt, int n, const zd* Ac, long ldac, doubl
     const int mq = jacobi_order_quantized(K);
     h->b_d.get<double>(mq);
     h->b_V.get<zd>((size_t)mq * mq);
-    h->b_jac.get<zd>(3 * (size_t)mq * mq);
+    h->b_jac.get<zd>(jacobi_work(mq));
     h->b_flag.get<int>(64);
   }
   zd* Rsel = h->b_Rsel.get<zd>((size_t)n * m0);

@@ -99,7 +99,7 @@ extern "C" int feast_kern_jacobi(const void* H, int m, double* d, void* W, void*
     int *flag, *rank;
     FEAST_HIP(hipMalloc(&Hc, sizeof(zd) * (size_t)m * m));
     FEAST_HIP(hipMalloc(&V, sizeof(zd) * (size_t)mp * mp));
-    FEAST_HIP(hipMalloc(&work, sizeof(zd) * 3 * (size_t)mp * mp));
+    FEAST_HIP(hipMalloc(&work, sizeof(zd) * jacobi_work(mp)));
     FEAST_HIP(hipMalloc(&dd, sizeof(double) * mp));
     FEAST_HIP(hipMalloc(&flag, 256));
     FEAST_HIP(hipMalloc(&rank, sizeof(int) * mp));

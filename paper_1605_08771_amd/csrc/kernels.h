@@ -112,8 +112,9 @@ void cholesky_upper(hipStream_t s, zd* G, int m, int ldg, int* flag, zd* tmp);
 // Rinv = R^{-1} for upper triangular R (m x m); Rinv must be zeroed by the call.
 void upper_inverse(hipStream_t s, const zd* R, int m, int ldr, zd* Rinv, int ldi, zd* tmp);
 // Cyclic parallel-order Jacobi on the Hermitian m x m matrix H (ld = m, destroyed).
+// A rotation is skipped when |h_pq| <= max(1e-17 sqrt(|h_pp h_qq|), eps ||H||_F).
 // Returns sweeps used (host sync per sweep) or -1.  d (device, mp) eigenvalues unsorted,
-// V (device, mp x mp, ld mp) eigenvectors; work: 3 mp^2 complex.
+// V (device, mp x mp, ld mp) eigenvectors; work: jacobi_work(mp) complex.
 // One sweep is recorded as a HIP graph (rounds, then a fill kernel and the check: no memset
 // node) and replayed per sweep when cache is given; the graph is re-recorded when the sizes
 // or buffers change.
@@ -130,6 +131,8 @@ struct JacobiGraph {
 int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* dflag,
                 int max_sweeps, JacobiGraph* cache, int mp);
 inline int jacobi_order(int m) { return m + (m & 1); }
+// Complex entries of jacobi_eigh's work array at padded order mp.
+inline size_t jacobi_work(int mp) { return 3 * (size_t)mp * mp + 40; }
 // A padded order on a coarse grid, so that recorded sweeps are reused across nearby sizes.
 inline int jacobi_order_quantized(int m) { return m <= 64 ? jacobi_order(m) : (m + 31) / 32 * 32; }
 // Stable ascending sort of d; Wout = V[:, order] (first m columns), lam = d[order].

@@ -143,13 +143,16 @@ struct Rot {
   zd e;  // e^{-i phi}, phi = arg(h_pq)
 };
 
-__device__ inline Rot make_rot(const zd* __restrict__ H, int mp, int p, int q) {
+// A rotation is skipped when |h_pq| <= max(1e-17 sqrt(|h_pp h_qq|), tol), tol = eps ||H||_F:
+// forming the reduced matrix already perturbs every entry by about eps ||H||, so rotating
+// smaller entries only chases rounding noise.
+__device__ inline Rot make_rot(const zd* __restrict__ H, int mp, int p, int q, double tol) {
   Rot r;
   zd hpq = H[p + (long)q * mp];
   double hpp = H[p + (long)p * mp].x, hqq = H[q + (long)q * mp].x;
   double a = sqrt(hpq.x * hpq.x + hpq.y * hpq.y);
   r.a = a;
-  r.active = !(a == 0.0 || a <= 1e-17 * sqrt(fabs(hpp * hqq)));
+  r.active = !(a == 0.0 || a <= 1e-17 * sqrt(fabs(hpp * hqq)) || a <= tol);
   if (!r.active) {
     r.c = 1;
     r.s = 0;
@@ -178,8 +181,10 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const zd* __restrict_
                                                            zd* __restrict__ Hout,
                                                            const zd* __restrict__ Vin,
                                                            zd* __restrict__ Vout, int mp,
-                                                           int round) {
+                                                           int round,
+                                                           const double* __restrict__ tolp) {
   const int half = mp / 2;
+  const double tol = tolp[0];
   long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   long nA = (long)half * half;
   if (idx < nA) {
@@ -187,8 +192,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const zd* __restrict_
     int pa, qa, pb, qb;
     pair_of(a, round, mp, pa, qa);
     pair_of(b, round, mp, pb, qb);
-    Rot ra = make_rot(Hin, mp, pa, qa);
-    Rot rb = (a == b) ? ra : make_rot(Hin, mp, pb, qb);
+    Rot ra = make_rot(Hin, mp, pa, qa, tol);
+    Rot rb = (a == b) ? ra : make_rot(Hin, mp, pb, qb, tol);
     zd b00 = Hin[pa + (long)pb * mp], b01 = Hin[pa + (long)qb * mp];
     zd b10 = Hin[qa + (long)pb * mp], b11 = Hin[qa + (long)qb * mp];
     // G = [[c, s], [-s e, c e]];  Y = G_a^H B
@@ -221,7 +226,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const zd* __restrict_
     int i = (int)(idx % mp), b = (int)(idx / mp);
     int pb, qb;
     pair_of(b, round, mp, pb, qb);
-    Rot rb = make_rot(Hin, mp, pb, qb);
+    Rot rb = make_rot(Hin, mp, pb, qb, tol);
     zd gb11 = zmake(rb.c, 0), gb12 = zmake(rb.s, 0);
     zd gb21 = zscale(rb.e, -rb.s), gb22 = zscale(rb.e, rb.c);
     zd v0 = Vin[i + (long)pb * mp], v1 = Vin[i + (long)qb * mp];
@@ -230,7 +235,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const zd* __restrict_
   }
 }
 
-__global__ void jacobi_check_kernel(const zd* __restrict__ H, int mp, int* flag) {
+__global__ void jacobi_check_kernel(const zd* __restrict__ H, int mp, const double* __restrict__ tolp,
+                                    int* flag) {
   long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (idx >= (long)mp * mp) return;
   int p = (int)(idx % mp), q = (int)(idx / mp);
@@ -238,7 +244,33 @@ __global__ void jacobi_check_kernel(const zd* __restrict__ H, int mp, int* flag)
   zd hpq = H[p + (long)q * mp];
   double a = sqrt(hpq.x * hpq.x + hpq.y * hpq.y);
   double hpp = H[p + (long)p * mp].x, hqq = H[q + (long)q * mp].x;
-  if (!(a == 0.0 || a <= 1e-17 * sqrt(fabs(hpp * hqq)))) atomicOr(flag, 1);
+  if (!(a == 0.0 || a <= 1e-17 * sqrt(fabs(hpp * hqq)) || a <= tolp[0])) atomicOr(flag, 1);
+}
+
+// tol = eps ||H||_F over the m x m input, in two deterministic stages (64 partial sums).
+__global__ __launch_bounds__(256) void fro_partial_kernel(const zd* __restrict__ H, long count,
+                                                          double* __restrict__ part) {
+  __shared__ double sh[256];
+  double s = 0;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < count; i += 256L * gridDim.x) {
+    zd v = H[i];
+    s += v.x * v.x + v.y * v.y;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void fro_final_kernel(const double* __restrict__ part, int nparts, double* tol) {
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int i = 0; i < nparts; ++i) s += part[i];
+    tol[0] = 2.220446049250313e-16 * sqrt(s);
+  }
 }
 
 __global__ void jacobi_init_kernel(const zd* __restrict__ H, int m, int mp, zd* __restrict__ A,
@@ -463,12 +495,13 @@ __global__ void copy_pair_kernel(const zd* __restrict__ a, zd* __restrict__ b, c
 
 // One sweep (mp - 1 rounds, ending on the buffers it started from) followed by the
 // convergence check, either launched directly or recorded into a graph by stream capture.
-static void jacobi_sweep_launches(hipStream_t s, zd* A0, zd* A1, zd* V0, zd* V1, int mp, int* dflag) {
+static void jacobi_sweep_launches(hipStream_t s, zd* A0, zd* A1, zd* V0, zd* V1, int mp, int* dflag,
+                                  const double* tolp) {
   const long nthreads = (long)(mp / 2) * (mp / 2) + (long)mp * (mp / 2);
   zd *Ain = A0, *Aout = A1, *Vin = V0, *Vout = V1;
   for (int r = 0; r < mp - 1; ++r) {
     hipLaunchKernelGGL(jacobi_round_kernel, grid1(nthreads), dim3(256), 0, s, Ain, Aout, Vin, Vout,
-                       mp, r);
+                       mp, r, tolp);
     std::swap(Ain, Aout);
     std::swap(Vin, Vout);
   }
@@ -477,7 +510,8 @@ static void jacobi_sweep_launches(hipStream_t s, zd* A0, zd* A1, zd* V0, zd* V1,
                        (long)mp * mp);
   }
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, dflag);
-  hipLaunchKernelGGL(jacobi_check_kernel, grid1((long)mp * mp), dim3(256), 0, s, A0, mp, dflag);
+  hipLaunchKernelGGL(jacobi_check_kernel, grid1((long)mp * mp), dim3(256), 0, s, A0, mp, tolp,
+                     dflag);
 }
 
 JacobiGraph::~JacobiGraph() {
@@ -487,12 +521,17 @@ JacobiGraph::~JacobiGraph() {
 
 int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* dflag,
                 int max_sweeps, JacobiGraph* cache, int mp) {
-  // work: 3 * mp * mp complex (A ping, A pong, V pong); V is mp x mp.
+  // work: 3 mp^2 + 40 complex (A ping, A pong, V pong; then 64 partial sums and tol as
+  // doubles); V is mp x mp.
   if (mp < jacobi_order(m) || (mp & 1)) mp = jacobi_order(m);
   zd* A0 = work;
   zd* A1 = work + (long)mp * mp;
   zd* V1 = work + 2L * mp * mp;
+  double* dwork = (double*)(work + 3L * mp * mp);
+  double* tolp = dwork + 64;
   hipLaunchKernelGGL(jacobi_init_kernel, grid1((long)mp * mp), dim3(256), 0, s, H, m, mp, A0, V);
+  hipLaunchKernelGGL(fro_partial_kernel, dim3(64), dim3(256), 0, s, H, (long)m * m, dwork);
+  hipLaunchKernelGGL(fro_final_kernel, dim3(1), dim3(64), 0, s, dwork, 64, tolp);
   FEAST_LAUNCH_CHECK();
   if (mp < 2) {
     hipLaunchKernelGGL(diag_kernel, dim3(1), dim3(64), 0, s, A0, mp, d);
@@ -508,7 +547,7 @@ int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* df
       cache->exec = cache->graph = nullptr;
       hipGraph_t g = nullptr;
       FEAST_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      jacobi_sweep_launches(s, A0, A1, V, V1, mp, dflag);
+      jacobi_sweep_launches(s, A0, A1, V, V1, mp, dflag, tolp);
       FEAST_HIP(hipStreamEndCapture(s, &g));
       hipGraphExec_t ge = nullptr;
       FEAST_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
@@ -525,7 +564,7 @@ int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* df
   bool converged = false;
   for (; sweeps < max_sweeps && !converged; ++sweeps) {
     if (exec) FEAST_HIP(hipGraphLaunch(exec, s));
-    else jacobi_sweep_launches(s, A0, A1, V, V1, mp, dflag);
+    else jacobi_sweep_launches(s, A0, A1, V, V1, mp, dflag, tolp);
     FEAST_LAUNCH_CHECK();
     int h = 0;
     FEAST_HIP(hipMemcpyAsync(&h, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
