@@ -42,7 +42,7 @@ SWEEP_TRAFFIC = {"sources": "6df62ef4736f4d94", "bytes_per_launch": 5.244e8}
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("gemm.hip", "solve.hip", "kernels.h", "common.h"):
+    for f in ("gemm.hip", "solve.hip", "feast_api.hip", "kernels.h", "common.h"):
         with open(os.path.join(ROOT, "paper_1605_08771_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

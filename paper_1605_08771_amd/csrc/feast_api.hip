@@ -251,6 +251,7 @@ int fail_hip(feast_ctx* h, const HipError& e) {
 }
 
 int pick_nbt(int n) {
+  if (n >= 8192) return 512;
   if (n >= 2048) return 256;
   if (n >= 384) return 128;
   return 64;

@@ -6,7 +6,11 @@
 // every MFMA flop is a useful flop of the 8-flop complex multiply-add.
 //
 // Tiling: 256 threads = 4 wave64s in a 2x2 grid, workgroup tile 64x64 complex outputs,
-// K-tile 16 complex, double-buffered LDS.  Operands are staged k-major so that lanes 0..15
+// K-tile 16 complex, double-buffered LDS, and two register sets so that the global loads of
+// K-tile kt+2 are in flight while K-tile kt is multiplied (one tile of compute, ~4k cycles,
+// does not cover HBM latency under load); the kernel is held to two waves per SIMD.  Within a
+// 4-deep k step the MFMAs are issued so that eight independent accumulators separate the two
+// products that feed the same one.  Operands are staged k-major so that lanes 0..15
 // of an MFMA fetch read 16 consecutive entries; LDS rows are padded by one entry so that
 // the transposing stores (k contiguous in HBM, k-major in LDS) hit 16 distinct banks.
 // Each wave owns 32x32 outputs (2x2 MFMA blocks).  The MFMA is fed with op(B)^T as its
@@ -137,11 +141,11 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
       DST = ldc_<v2, OPB == OP_C>(B + gj + (long)gk * ldb, gj < N && gk < K);        \
     }                                                                                \
   }
-#define FEAST_LOAD_TILE(K0)                                                          \
+#define FEAST_LOAD_TILE_INTO(K0, A0, A1, A2, A3, B0, B1, B2, B3)                    \
   {                                                                                  \
     const int k0 = (K0);                                                             \
-    FEAST_LOAD_A(0, ra0) FEAST_LOAD_A(1, ra1) FEAST_LOAD_A(2, ra2) FEAST_LOAD_A(3, ra3) \
-    FEAST_LOAD_B(0, rb0) FEAST_LOAD_B(1, rb1) FEAST_LOAD_B(2, rb2) FEAST_LOAD_B(3, rb3) \
+    FEAST_LOAD_A(0, A0) FEAST_LOAD_A(1, A1) FEAST_LOAD_A(2, A2) FEAST_LOAD_A(3, A3)  \
+    FEAST_LOAD_B(0, B0) FEAST_LOAD_B(1, B1) FEAST_LOAD_B(2, B2) FEAST_LOAD_B(3, B3)  \
   }
 #define FEAST_STORE_AB(R, SA, SB)                                                    \
   {                                                                                  \
@@ -150,13 +154,34 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
     if (OPB == OP_N) Bs[buf_][t & 15][(t >> 4) + 16 * (R)] = SB;                     \
     else Bs[buf_][(t >> 6) + 4 * (R)][t & 63] = SB;                                  \
   }
-#define FEAST_STORE_TILE(BUF)                                                        \
+#define FEAST_STORE_TILE_FROM(BUF, A0, A1, A2, A3, B0, B1, B2, B3)                  \
   {                                                                                  \
     const int buf_ = (BUF);                                                          \
-    FEAST_STORE_AB(0, ra0, rb0) FEAST_STORE_AB(1, ra1, rb1)                          \
-    FEAST_STORE_AB(2, ra2, rb2) FEAST_STORE_AB(3, ra3, rb3)                          \
+    FEAST_STORE_AB(0, A0, B0) FEAST_STORE_AB(1, A1, B1)                              \
+    FEAST_STORE_AB(2, A2, B2) FEAST_STORE_AB(3, A3, B3)                              \
   }
-
+#define FEAST_COMPUTE(BUF)                                                           \
+  {                                                                                  \
+    const int buf = (BUF);                                                           \
+    _Pragma("unroll") for (int kk = 0; kk < BK / 4; ++kk) {                          \
+      const int kidx = kk * 4 + (lane >> 4);                                         \
+      v2 fa[2], fb[2];                                                               \
+      _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                               \
+        fa[mb] = As[buf][kidx][wm * 32 + mb * 16 + (lane & 15)];                      \
+      _Pragma("unroll") for (int nb = 0; nb < 2; ++nb)                               \
+        fb[nb] = Bs[buf][kidx][wn * 32 + nb * 16 + (lane & 15)];                      \
+      _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                               \
+        _Pragma("unroll") for (int nb = 0; nb < 2; ++nb) {                           \
+          accr[mb][nb] = mfma(fb[nb].x, fa[mb].x, accr[mb][nb]);                     \
+          acci[mb][nb] = mfma(fb[nb].x, fa[mb].y, acci[mb][nb]);                     \
+        }                                                                            \
+      _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                               \
+        _Pragma("unroll") for (int nb = 0; nb < 2; ++nb) {                           \
+          accr[mb][nb] = mfma(-fb[nb].y, fa[mb].y, accr[mb][nb]);                    \
+          acci[mb][nb] = mfma(fb[nb].y, fa[mb].x, acci[mb][nb]);                     \
+        }                                                                            \
+    }                                                                                \
+  }
   accv accr[2][2], acci[2][2];
 #pragma unroll
   for (int p = 0; p < 2; ++p)
@@ -167,40 +192,31 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
     }
 
   const int nkt = (K + BK - 1) / BK;
+  v2 qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3;
+  // prefetch distance two: tile kt+2 is in flight while tile kt is multiplied
   if (nkt > 0) {
-    FEAST_LOAD_TILE(0)
-    FEAST_STORE_TILE(0)
+    FEAST_LOAD_TILE_INTO(0, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)
+    FEAST_STORE_TILE_FROM(0, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)
   }
+  if (nkt > 1) FEAST_LOAD_TILE_INTO(BK, qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3)
   __syncthreads();
-  for (int kt = 0; kt < nkt; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nkt) FEAST_LOAD_TILE((kt + 1) * BK)
-#pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
-      const int kidx = kk * 4 + (lane >> 4);
-      v2 fa[2], fb[2];
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb) fa[mb] = As[buf][kidx][wm * 32 + mb * 16 + (lane & 15)];
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) fb[nb] = Bs[buf][kidx][wn * 32 + nb * 16 + (lane & 15)];
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-          accr[mb][nb] = mfma(fb[nb].x, fa[mb].x, accr[mb][nb]);
-          accr[mb][nb] = mfma(-fb[nb].y, fa[mb].y, accr[mb][nb]);
-          acci[mb][nb] = mfma(fb[nb].x, fa[mb].y, acci[mb][nb]);
-          acci[mb][nb] = mfma(fb[nb].y, fa[mb].x, acci[mb][nb]);
-        }
-    }
-    if (kt + 1 < nkt) FEAST_STORE_TILE(buf ^ 1)
+  for (int kt = 0; kt < nkt; kt += 2) {
+    if (kt + 2 < nkt) FEAST_LOAD_TILE_INTO((kt + 2) * BK, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)
+    FEAST_COMPUTE(0)
+    if (kt + 1 < nkt) FEAST_STORE_TILE_FROM(1, qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3)
+    __syncthreads();
+    if (kt + 1 >= nkt) break;
+    if (kt + 3 < nkt) FEAST_LOAD_TILE_INTO((kt + 3) * BK, qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3)
+    FEAST_COMPUTE(1)
+    if (kt + 2 < nkt) FEAST_STORE_TILE_FROM(0, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)
     __syncthreads();
   }
 #undef FEAST_LOAD_A
 #undef FEAST_LOAD_B
-#undef FEAST_LOAD_TILE
+#undef FEAST_LOAD_TILE_INTO
+#undef FEAST_COMPUTE
 #undef FEAST_STORE_AB
-#undef FEAST_STORE_TILE
+#undef FEAST_STORE_TILE_FROM
 
   const v2 alpha = a.alpha, beta = a.beta;
   const bool beta_zero = (beta.x == T(0) && beta.y == T(0));
@@ -228,7 +244,7 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
 }
 
 template <typename T, int OPA0, int OPA1, int OPB>
-__global__ __launch_bounds__(NT) void gemm_kernel(const Args<typename CT<T>::v2> a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void gemm_kernel(const Args<typename CT<T>::v2> a) {
   typedef typename CT<T>::v2 v2;
   __shared__ v2 As[2][BK][BM + PAD];
   __shared__ v2 Bs[2][BK][BN + PAD];
