@@ -322,14 +322,14 @@ __global__ __launch_bounds__(256) void laswp_kernel(typename V2<T>::t* __restric
 // U12 = L11^{-1} A12 for 64 columns per workgroup (L11 unit lower, staged in LDS).
 template <typename T>
 __global__ __launch_bounds__(256) void trsm_u12_kernel(typename V2<T>::t* __restrict__ M, int np,
-                                                       int k, int w) {
+                                                       int k, int w, int c0, int c1) {
   typedef typename V2<T>::t v2;
   __shared__ v2 L[NBP][NBP + 1];
   __shared__ v2 X[NBP][NBP + 1];
   const int node = blockIdx.y;
   M += (long)node * np * np;
   const int t = threadIdx.x;
-  const int col0 = k + w + blockIdx.x * 64;
+  const int col0 = c0 + blockIdx.x * 64;
   for (int e = t; e < w * w; e += 256) {
     int r = e % w, cc = e / w;
     L[r][cc] = M[k + r + (long)(k + cc) * np];
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(256) void trsm_u12_kernel(typename V2<T>::t* __rest
   for (int e = t; e < w * 64; e += 256) {
     int r = e % w, cc = e / w;
     int gc = col0 + cc;
-    X[r][cc] = (gc < np) ? M[k + r + (long)gc * np] : v2{0, 0};
+    X[r][cc] = (gc < c1) ? M[k + r + (long)gc * np] : v2{0, 0};
   }
   __syncthreads();
   for (int r = 0; r < w - 1; ++r) {
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(256) void trsm_u12_kernel(typename V2<T>::t* __rest
   for (int e = t; e < w * 64; e += 256) {
     int r = e % w, cc = e / w;
     int gc = col0 + cc;
-    if (gc < np) M[k + r + (long)gc * np] = X[r][cc];
+    if (gc < c1) M[k + r + (long)gc * np] = X[r][cc];
   }
 }
 
@@ -369,26 +369,27 @@ __global__ void perm_invert_kernel(const int* perm, int* pinv, int np, int nc) {
   }
 }
 
+// M[r0:r0+rows, c0:c0+cols] -= M[r0:r0+rows, k:k+kw] * M[k:k+kw, c0:c0+cols] for every node.
 template <typename T>
-void gemm_update(hipStream_t s, typename V2<T>::t* M, int np, int nc, int k, int w);
+void gemm_update(hipStream_t s, typename V2<T>::t* M, int np, int nc, int r0, int rows, int c0,
+                 int cols, int k, int kw);
 template <>
-void gemm_update<double>(hipStream_t s, zd* M, int np, int nc, int k, int w) {
-  int rest = np - k - w;
+void gemm_update<double>(hipStream_t s, zd* M, int np, int nc, int r0, int rows, int c0, int cols,
+                         int k, int kw) {
   Batch b;
   b.n1 = nc;
   b.sA1 = b.sB1 = b.sC1 = (long)np * np;
-  zgemm(s, OP_N, OP_N, rest, rest, w, zmake(-1, 0), M + (k + w) + (long)k * np, np,
-        M + k + (long)(k + w) * np, np, zmake(1, 0), M + (k + w) + (long)(k + w) * np, np, b);
+  zgemm(s, OP_N, OP_N, rows, cols, kw, zmake(-1, 0), M + r0 + (long)k * np, np,
+        M + k + (long)c0 * np, np, zmake(1, 0), M + r0 + (long)c0 * np, np, b);
 }
 template <>
-void gemm_update<float>(hipStream_t s, zf* M, int np, int nc, int k, int w) {
-  int rest = np - k - w;
+void gemm_update<float>(hipStream_t s, zf* M, int np, int nc, int r0, int rows, int c0, int cols,
+                        int k, int kw) {
   Batch b;
   b.n1 = nc;
   b.sA1 = b.sB1 = b.sC1 = (long)np * np;
-  cgemm(s, OP_N, OP_N, rest, rest, w, make_float2(-1, 0), M + (k + w) + (long)k * np, np,
-        M + k + (long)(k + w) * np, np, make_float2(1, 0), M + (k + w) + (long)(k + w) * np, np,
-        b);
+  cgemm(s, OP_N, OP_N, rows, cols, kw, make_float2(-1, 0), M + r0 + (long)k * np, np,
+        M + k + (long)c0 * np, np, make_float2(1, 0), M + r0 + (long)c0 * np, np, b);
 }
 
 template <typename T>
@@ -401,32 +402,53 @@ void lu_factor(hipStream_t s, typename V2<T>::t* M, int np, int nc, LuWork& w) {
     hipLaunchKernelGGL(perm_init_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, w.perm, np, nc);
     FEAST_LAUNCH_CHECK();
   }
-  for (int k = 0; k < np; k += NBP) {
-    const int width = (np - k < NBP) ? np - k : NBP;
-    const int nwg = (np - k + RPW - 1) / RPW;
+  // Factor one 64-wide panel starting at column kp (pivot search, implicit-pivoting column
+  // steps, row moves applied across all columns).
+  auto factor_panel = [&](int kp, int width) {
+    const int nwg = (np - kp + RPW - 1) / RPW;
     double* pv[2] = {w.pval, w.pval + nc * maxwg};
     int* pr[2] = {w.prow, w.prow + nc * maxwg};
-    hipLaunchKernelGGL((panel_search_kernel<T>), dim3(nwg, nc), dim3(RPW), 0, s, M, np, k, pv[0],
+    hipLaunchKernelGGL((panel_search_kernel<T>), dim3(nwg, nc), dim3(RPW), 0, s, M, np, kp, pv[0],
                        pr[0], maxwg);
     FEAST_LAUNCH_CHECK();
     for (int jj = 0; jj < width; ++jj) {
-      hipLaunchKernelGGL((panel_step_kernel<T>), dim3(nwg, nc), dim3(RPW), 0, s, M, np, k, width,
+      hipLaunchKernelGGL((panel_step_kernel<T>), dim3(nwg, nc), dim3(RPW), 0, s, M, np, kp, width,
                          jj, nwg, maxwg, pv[jj & 1], pr[jj & 1], pv[(jj + 1) & 1],
                          pr[(jj + 1) & 1], w.retired, w.pivrows, w.flag);
       FEAST_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(panel_moves_kernel, dim3(nc), dim3(128), 0, s, np, k, width, w.pivrows,
+    hipLaunchKernelGGL(panel_moves_kernel, dim3(nc), dim3(128), 0, s, np, kp, width, w.pivrows,
                        w.moves, w.perm);
     FEAST_LAUNCH_CHECK();
     hipLaunchKernelGGL((laswp_kernel<T>), dim3((np + SWAP_COLS - 1) / SWAP_COLS, nc), dim3(256),
                        0, s, M, np, w.moves);
     FEAST_LAUNCH_CHECK();
-    const int rest = np - k - width;
-    if (rest > 0) {
-      hipLaunchKernelGGL((trsm_u12_kernel<T>), dim3((rest + 63) / 64, nc), dim3(256), 0, s, M, np,
-                         k, width);
-      FEAST_LAUNCH_CHECK();
-      gemm_update<T>(s, M, np, nc, k, width);
+  };
+  // U12 = L11^{-1} M[kp:kp+width, c0:c1] with the unit-lower diagonal block of panel kp.
+  auto trsm = [&](int kp, int width, int c0, int c1) {
+    hipLaunchKernelGGL((trsm_u12_kernel<T>), dim3((c1 - c0 + 63) / 64, nc), dim3(256), 0, s, M,
+                       np, kp, width, c0, c1);
+    FEAST_LAUNCH_CHECK();
+  };
+  // Outer panels of two 64-wide sub-panels: the trailing update then contracts over 128
+  // columns at once (half the read-modify-write traffic of two 64-deep updates).
+  for (int k = 0; k < np; k += 2 * NBP) {
+    const int w0 = (np - k < NBP) ? np - k : NBP;
+    const int w1 = (np - k - w0 < NBP) ? np - k - w0 : NBP;
+    factor_panel(k, w0);
+    if (w1 > 0) {  // bring sub-panel 1 up to date, then factor it
+      trsm(k, w0, k + w0, k + w0 + w1);
+      gemm_update<T>(s, M, np, nc, k + w0, np - k - w0, k + w0, w1, k, w0);
+      factor_panel(k + w0, w1);
+    }
+    const int c = k + w0 + w1;
+    if (c < np) {
+      trsm(k, w0, c, np);
+      if (w1 > 0) {
+        gemm_update<T>(s, M, np, nc, k + w0, w1, c, np - c, k, w0);
+        trsm(k + w0, w1, c, np);
+      }
+      gemm_update<T>(s, M, np, nc, c, np - c, c, np - c, k, w0 + w1);
     }
   }
   long tot = (long)np * nc;
