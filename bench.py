@@ -36,7 +36,7 @@ PEAK_HBM = 8000.0      # GB/s
 # HBM bytes per launch of the paired sweep GEMM on the default workload (FP64, n=8192), from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy of known size; valid only
 # while the sources of that kernel are the ones the counters were taken on.
-SWEEP_TRAFFIC = {"sources": "6df62ef4736f4d94", "bytes_per_launch": 5.244e8}
+SWEEP_TRAFFIC = {"sources": "ba3005f81a9fd333", "bytes_per_launch": 8.601e8}
 
 
 def kernel_sources_hash():
