@@ -31,6 +31,7 @@ METRIC = "FEAST time-to-solution (res≤1e-10‖A‖) + filter-apply TFLOP/s, mi
 PEAK_FP64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix
 PEAK_FP32_MFMA = 157.3
 PEAK_HBM = 8000.0      # GB/s
+PRECS = {"fp64": 0, "fp32ir": 1, "bf16x3ir": 2}
 
 
 # HBM bytes per launch of the paired sweep GEMM on the default workload (FP64, n=8192), from
@@ -117,7 +118,7 @@ def bench_batched(args, dev):
     probs = [gen.config4_problem(sp, device=dev) for sp in specs]
     log(f"[bench] generated {len(probs)} problems in {time.time() - t0:.1f}s")
     prec_name = args.prec or "fp32ir"
-    prec = fm.FEAST_FP32_IR if prec_name == "fp32ir" else fm.FEAST_FP64
+    prec = PRECS[prec_name]
     d = [dict(A=p.A, X0=p.X0, emin=p.emin, emax=p.emax, m0=p.m0, anorm=p.anorm) for p in probs]
     f = fm.Feast()
 
@@ -201,7 +202,11 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--nstreams", type=int, default=8, help="c4: concurrent worker streams")
     ap.add_argument("--n", type=int, default=0, help="override n (tests only)")
-    ap.add_argument("--prec", default="", choices=["", "fp64", "fp32ir"])
+    ap.add_argument("--prec", default="", choices=["", *PRECS])
+    ap.add_argument("--compare", default=None,
+                    help="comma-separated precisions run after the timed steps on the same "
+                         "input and threshold (default: the other of fp64/fp32ir; c3 adds "
+                         "bf16x3ir, the split-precision factorization)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the run in the other precision")
@@ -226,7 +231,7 @@ def main():
         return bench_batched(args, dev)
     p = make_problem(args, dev)
     prec_name = args.prec or ("fp32ir" if args.workload == "c3" else "fp64")
-    prec = fm.FEAST_FP32_IR if prec_name == "fp32ir" else fm.FEAST_FP64
+    prec = PRECS[prec_name]
     A = p.A
     X0 = p.X0
     f = fm.Feast()
@@ -297,23 +302,35 @@ def main():
     filter_tflops = alg_filter / (filt_ms * 1e-3) / 1e12 if filt_ms > 0 else 0.0
     f.set_profiling(False)
 
-    # the other precision on the same input, to the same threshold (mixed vs FP64)
-    other = fm.FEAST_FP64 if prec == fm.FEAST_FP32_IR else fm.FEAST_FP32_IR
-    other_name = "fp64" if other == fm.FEAST_FP64 else "fp32ir"
-    compare = None
-    if not args.no_compare:
+    # other precisions on the same input, to the same threshold (mixed vs FP64)
+    cspec = args.compare
+    if cspec is None:
+        cspec = "fp32ir" if prec_name == "fp64" else "fp64"
+        if args.workload == "c3":
+            cspec += ",bf16x3ir"
+    compares = []
+    for other_name in [c for c in cspec.split(",") if c and c != prec_name]:
+        if args.no_compare:
+            break
+        other = PRECS[other_name]
         one(1e-10, pr=other)  # warm-up of the other path's buffers
+        f.set_profiling(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         o2 = one(1e-10, pr=other)
         torch.cuda.synchronize()
         t_other = time.perf_counter() - t0
+        lu2, solve2 = f.kernel_stats("lu"), f.kernel_stats("solve")
+        f.set_profiling(False)
         ok2, err2, res2 = check(o2, 1e-10)
-        compare = {"precision": other_name, "time_s": round(t_other, 4), "iterations": o2["iters"],
-                   "correct": ok2, "max_eig_err": err2, "max_residual": res2,
-                   "phase_ms": {k: round(v, 2) for k, v in f.timings().items()},
-                   "speedup_of_value_path": round(t_other / (total / args.steps), 3)}
-        log(f"[bench] {other_name}: {compare}")
+        rec = {"precision": other_name, "time_s": round(t_other, 4), "iterations": o2["iters"],
+               "correct": ok2, "max_eig_err": err2, "max_residual": res2,
+               "phase_ms": {k: round(v, 2) for k, v in f.timings().items()},
+               "lu_gemm_ms": round(lu2["ms"], 2), "solve_gemm_ms": round(solve2["ms"], 2),
+               "speedup_of_value_path": round(t_other / (total / args.steps), 3)}
+        compares.append(rec)
+        log(f"[bench] {other_name}: {rec}")
+    compare = compares[0] if compares else None
     # the expanded-subspace variants of Sec. 2 on the same input and threshold
     variants = []
     vspec = args.variants
@@ -403,6 +420,7 @@ def main():
         "eigensolves": {"ms": round(eig_main["ms"], 2), "sweeps": eig_main["launches"],
                         "calls": int(eig_main["dense_flops"])},
         "other_precision": compare,
+        "more_precisions": compares[1:],
         "variants": variants,
         "cpu_baseline": cpu,
     }

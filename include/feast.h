@@ -50,8 +50,12 @@ typedef enum { FEAST_R64 = 0, FEAST_C128 = 1 } feast_dtype;
 /* Arithmetic of the shifted factorizations and solves.  FEAST_FP64: everything in FP64.
  * FEAST_FP32_IR: LU factors and correction solves in FP32 complex (FP32 matrix cores), with
  * iterative refinement whose residuals X - (z_j I - A) Y and updates are FP64, to the FP64
- * accuracy of the filtered block.  The Rayleigh-Ritz step is FP64 in both modes. */
-typedef enum { FEAST_FP64 = 0, FEAST_FP32_IR = 1 } feast_precision;
+ * accuracy of the filtered block.  FEAST_BF16X3_IR: as FEAST_FP32_IR (FP32 factor storage,
+ * same refinement), but the matrix-core products of the factorization and of the solves split
+ * each FP32 operand into bf16 hi + lo parts and sum three bf16 products (hi hi, hi lo, lo hi)
+ * in FP32, about 16 significant bits per product.  The Rayleigh-Ritz step is FP64 in every
+ * mode. */
+typedef enum { FEAST_FP64 = 0, FEAST_FP32_IR = 1, FEAST_BF16X3_IR = 2 } feast_precision;
 
 /* The subspace iteration run by feast_solve.
  * FEAST_METHOD_FEAST: the FEAST algorithm (Appendix).
@@ -78,7 +82,7 @@ typedef struct {
   int n_c;          /* quadrature nodes on the upper half circle (>= 1) */
   int m0;           /* subspace size, more than the number of eigenvalues in I */
   int max_iter;     /* FEAST iterations (>= 1) */
-  int refine_max;   /* FP32_IR: classic refinement steps (FP64 residual with A) when the
+  int refine_max;   /* FP32_IR, BF16X3_IR: classic refinement steps (FP64 residual with A) when the
                        filter has no Ritz information, i.e. the first iteration (>= 0) */
   double tol;       /* stop when max residual over Ritz values in I <= tol (> 0) */
   double anorm;     /* ||A||_2 used to scale residuals; <= 0: estimated by power iteration */
@@ -91,7 +95,7 @@ typedef struct {
                        t = (lambda - c)/r, so rho > 1/2 exactly on I and a Ritz vector built
                        from eigenvectors outside I has mu < 1/2.  mu_k is read off the next
                        iteration's filtered block, so a converged run applies the filter once
-                       more than it runs Rayleigh-Ritz.  FEAST_FP32_IR always applies this
+                       more than it runs Rayleigh-Ritz.  The mixed modes always apply this
                        test: FP32 solves leave the strongly damped directions of the filtered
                        block at the FP32 noise floor, and Rayleigh-Ritz turns that noise into
                        Ritz pairs inside I with large residuals. */
@@ -209,7 +213,7 @@ typedef struct {
   int* iters;        /* host */
   int* status;       /* host: the feast_solve return code of this problem */
   double* mu;        /* host, m0, or NULL: filter values mu_k of the returned Ritz vectors
-                        (written when opt->spurious = 1 or opt->prec = FEAST_FP32_IR) */
+                        (written when opt->spurious = 1 or opt->prec is a mixed mode) */
 } feast_problem;
 
 /* Independent FEAST problems (Sec. 1: disjoint intervals, or independent matrices, are solved
@@ -230,7 +234,7 @@ int feast_get_filter_values(feast_handle h, double* mu, int m0);
 /* Phase timings of the last feast_solve / feast_filter_apply / feast_rayleigh_ritz call, in
  * milliseconds measured with HIP events on the handle's stream:
  * out[0] factorization (shift + LU + diagonal-block inverses), out[1] triangular solves,
- * out[2] accumulation, out[3] Rayleigh-Ritz, out[4] refinement (FP32_IR), out[5] total.
+ * out[2] accumulation, out[3] Rayleigh-Ritz, out[4] refinement (mixed modes), out[5] total.
  * Returns the number of values written (<= count). */
 int feast_get_timings(feast_handle h, double* out, int count);
 

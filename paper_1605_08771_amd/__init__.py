@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfeast_mi355x.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "feast.h")
 
 FEAST_R64, FEAST_C128 = 0, 1
-FEAST_FP64, FEAST_FP32_IR = 0, 1
+FEAST_FP64, FEAST_FP32_IR, FEAST_BF16X3_IR = 0, 1, 2
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "M0_TOO_SMALL", 3: "NO_EIGENVALUES",
           4: "B_NOT_SPD", 5: "NONFINITE", 6: "ZERO_PIVOT", -100: "ERR_ALLOC",
           -101: "ERR_HIP", -102: "ERR_UNSUPPORTED"}
@@ -254,7 +254,7 @@ class Feast:
                                trace.ctypes.data_as(_dp))
         out = dict(status=st, X=X, lam=lam, res=res, m=m.value, iters=iters.value,
                    trace=trace[: iters.value])
-        if spurious or prec == FEAST_FP32_IR:
+        if spurious or prec != FEAST_FP64:
             mu = np.zeros(m0)
             lib().feast_get_filter_values(self.h, mu.ctypes.data_as(_dp), m0)
             out["mu"] = mu
@@ -387,19 +387,23 @@ class Feast:
         found = []
         for i, o in enumerate(outs):
             ok = (o["lam"] > edges[i]) & (o["lam"] < edges[i + 1])
-            if spurious or prec == FEAST_FP32_IR:
+            if spurious or prec != FEAST_FP64:
                 ok &= o["mu"] > 0.5
             o["counted"] = np.flatnonzero(ok)
             found.append(o["lam"][ok])
         return bad, outs, np.sort(np.concatenate(found)) if found else np.zeros(0)
 
     # ---------------------------------------------------------------- building blocks
-    def gemm(self, opA, opB, A, B, C, alpha=1.0, beta=0.0, M=None, N=None, K=None):
-        """C = alpha op(A) op(B) + beta C on the matrix cores (complex128 or complex64)."""
+    def gemm(self, opA, opB, A, B, C, alpha=1.0, beta=0.0, M=None, N=None, K=None,
+             split_bf16=False):
+        """C = alpha op(A) op(B) + beta C on the matrix cores (complex128 or complex64;
+        split_bf16 with complex64: bf16x3 products with FP32 accumulation)."""
         import torch
         if A.dtype not in (torch.complex128, torch.complex64):
             raise TypeError("gemm takes complex128 or complex64 operands")
-        prec = 0 if A.dtype == torch.complex128 else 1
+        if split_bf16 and A.dtype != torch.complex64:
+            raise TypeError("split_bf16 takes complex64 operands")
+        prec = 0 if A.dtype == torch.complex128 else (2 if split_bf16 else 1)
         M = C.shape[0] if M is None else M
         N = C.shape[1] if N is None else N
         if K is None:
@@ -417,8 +421,9 @@ class Feast:
         return st
 
     def lu(self, A, z, prec=0):
-        """Factors of z_j I - A for the nodes z (numpy complex array).  Returns
-        (status, LU [nc, np, np] tensor in column-major blocks, perm [nc, np])."""
+        """Factors of z_j I - A for the nodes z (numpy complex array); prec 0 FP64, 1 FP32,
+        2 FP32 with bf16x3 trailing updates.  Returns (status, LU [nc, np, np] tensor in
+        column-major blocks, perm [nc, np])."""
         import numpy as np
         import torch
         _need(A, "A", torch.complex128)

@@ -309,6 +309,8 @@ int ensure_factors(feast_ctx* h, int dt, int n, const void* A, int lda, double e
       tri_inverse_blocks_f64(s, F, np, nc, nbt, iL, iU, tmp);
     }
   } else {
+    // FEAST_BF16X3_IR: the FP32 factorization's matrix-core products run as bf16x3.
+    SplitBf16Scope split(prec == FEAST_BF16X3_IR);
     zf* F = h->b_fac.get<zf>((size_t)nc * np * np);
     shift_matrices_f32(s, A, lda, dt == FEAST_R64, n, np, zdev, nc, F, B, ldb);
     {
@@ -426,7 +428,8 @@ int filter_core(feast_ctx* h, int dt, int n, int m0, const zd* X, long ldx, zd* 
     h->timer.add(e1, e2, P_ACC);
     return 0;
   }
-  // FP32 factors
+  // FP32 factors (and, for FEAST_BF16X3_IR, bf16x3 products in the sweeps)
+  SplitBf16Scope split(h->f_prec == FEAST_BF16X3_IR);
   zf* B32 = h->b_B.get<zf>(blk);
   zf* Z32 = h->b_Z.get<zf>(blk);
   const zf* F = (const zf*)h->b_fac.p;
@@ -763,7 +766,7 @@ int xr_solve(feast_ctx* h, feast_dtype dt, int n, const zd* Ac, long ldac, doubl
   hipStream_t s = h->stream;
   const int m0 = opt->m0, sx = opt->expand, variant = opt->method;
   const int K = sx * m0;
-  const bool mixed = opt->prec == FEAST_FP32_IR;
+  const bool mixed = opt->prec != FEAST_FP64;
   const bool spur = opt->spurious != 0 || mixed;
   // Buffers sized once for the widest basis, so device pointers (and the recorded Jacobi
   // sweeps that capture them) stay fixed while the basis width changes.
@@ -993,7 +996,7 @@ int feast_filter_apply(feast_handle h, feast_dtype dt, int n, const void* A, int
   if (!std::isfinite(emin)) return -6;
   if (!std::isfinite(emax) || !(emin < emax)) return -7;
   if (n_c < 1 || n_c > 128) return -8;
-  if (prec != FEAST_FP64 && prec != FEAST_FP32_IR) return -9;
+  if (prec != FEAST_FP64 && prec != FEAST_FP32_IR && prec != FEAST_BF16X3_IR) return -9;
   if (!X) return -10;
   if (ldx < n) return -11;
   if (m0 < 1 || m0 > n) return -12;
@@ -1026,8 +1029,11 @@ int feast_filter_apply(feast_handle h, feast_dtype dt, int n, const void* A, int
       ldqc = ldq;
     }
     long ldac = lda;
-    const zd* Ac = (prec == FEAST_FP32_IR) ? complex_A(h, dt, n, A, lda, &ldac) : nullptr;
-    st = filter_core(h, dt, n, m0, Xc, ldxc, Qc, ldqc, Ac, ldac, nullptr, 2);
+    const zd* Ac = (prec != FEAST_FP64) ? complex_A(h, dt, n, A, lda, &ldac) : nullptr;
+    // Classic refinement: each step contracts the error by ~kappa(z_j I - A) times the
+    // products' relative accuracy (2^-24 FP32, ~2^-16 bf16x3).
+    st = filter_core(h, dt, n, m0, Xc, ldxc, Qc, ldqc, Ac, ldac, nullptr,
+                     prec == FEAST_BF16X3_IR ? 4 : 2);
     if (st == 0 && dt == FEAST_R64) complex_to_real(s, Qc, n, (double*)Q, ldq, n, m0);
     hipEvent_t t1 = h->timer.mark(s);
     h->timer.add(t0, t1, P_TOTAL);
@@ -1134,9 +1140,9 @@ int solve_impl(feast_handle h, feast_dtype dt, int n, const void* A, int lda, co
     // FP32 factors leave the filtered block's damped directions (|rho| far below the FP32
     // noise floor) as noise, which Rayleigh-Ritz turns into Ritz pairs inside I with large
     // residuals; the filter-value test rejects them, so FP32_IR always applies it.
-    const bool spur = opt->spurious != 0 || opt->prec == FEAST_FP32_IR;
+    const bool spur = opt->spurious != 0 || opt->prec != FEAST_FP64;
     h->mu.assign(m0, 0.0);
-    const bool mixed = opt->prec == FEAST_FP32_IR;
+    const bool mixed = opt->prec != FEAST_FP64;
     zd* Reig = mixed ? h->b_Reig.get<zd>((size_t)n * m0) : nullptr;
     RitzInfo ri{Reig, nullptr};
     int fs = filter_core(h, dt, n, m0, rhs(Xw), n, Qf, n, Ac, ldac, nullptr,
@@ -1232,8 +1238,9 @@ int feast_solve(feast_handle h, feast_dtype dt, int n, const void* A, int lda, d
   if (!std::isfinite(emax) || !(emin < emax)) return -7;
   if (!opt || opt->n_c < 1 || opt->n_c > 128 || opt->m0 < 1 || opt->m0 > n ||
       opt->max_iter < 1 || !(opt->tol > 0) ||
-      (opt->prec != FEAST_FP64 && opt->prec != FEAST_FP32_IR) ||
-      (opt->prec == FEAST_FP32_IR && opt->refine_max < 0) ||
+      (opt->prec != FEAST_FP64 && opt->prec != FEAST_FP32_IR &&
+       opt->prec != FEAST_BF16X3_IR) ||
+      (opt->prec != FEAST_FP64 && opt->refine_max < 0) ||
       (opt->method != FEAST_METHOD_FEAST && opt->method != FEAST_METHOD_XFEAST &&
        opt->method != FEAST_METHOD_RFEAST) ||
       (opt->method != FEAST_METHOD_FEAST &&

@@ -31,6 +31,7 @@
 namespace feast {
 
 thread_local GemmProfiler* g_gemm_prof = nullptr;
+thread_local bool g_split_bf16 = false;
 
 namespace {
 
@@ -301,6 +302,260 @@ void dispatch(hipStream_t s, const int* opA, int nprob, int opB,
   if (prof) prof->end(s, flops);
 }
 
+// ---- bf16x3: FP32 complex operands split into bf16 hi + lo -------------------------------
+// Each FP32 value x is stored as hi = bf16(x) and lo = bf16(x - hi) (round to nearest even);
+// a real product is hi*hi + hi*lo + lo*hi (the lo*lo term, ~2^-16 relative, is dropped) on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  Per 32-deep step a 16x16 complex block
+// takes 12 of these MFMAs: real part re*re - im*im and imaginary part re*im + im*re, each
+// real product three-fold.  LDS holds four bf16 planes (re hi, re lo, im hi, im lo) per
+// operand with the 32 k values of a row contiguous, in 16-byte chunks whose position is
+// XOR-swizzled by (row >> 2) so that the 16 rows one MFMA operand read touches hit distinct
+// banks.  Operand roles and the C^T epilogue are those of gemm_tile above; the MFMA result
+// layout is the FP32 one (row 4 (l >> 4) + v).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int XBK = 32;
+
+__device__ __forceinline__ unsigned bf16_rne_bits(float x) {  // finite x
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+// 8 consecutive-k complex values -> four 16-byte chunks (re hi, re lo, im hi, im lo).
+__device__ __forceinline__ void split8(const float2 (&v)[8], uint4 (&o)[4]) {
+  unsigned rh[8], rl[8], ih[8], il[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    unsigned h = bf16_rne_bits(v[e].x);
+    rh[e] = h;
+    rl[e] = bf16_rne_bits(v[e].x - __uint_as_float(h << 16));
+    h = bf16_rne_bits(v[e].y);
+    ih[e] = h;
+    il[e] = bf16_rne_bits(v[e].y - __uint_as_float(h << 16));
+  }
+  o[0] = make_uint4(rh[0] | (rh[1] << 16), rh[2] | (rh[3] << 16), rh[4] | (rh[5] << 16),
+                    rh[6] | (rh[7] << 16));
+  o[1] = make_uint4(rl[0] | (rl[1] << 16), rl[2] | (rl[3] << 16), rl[4] | (rl[5] << 16),
+                    rl[6] | (rl[7] << 16));
+  o[2] = make_uint4(ih[0] | (ih[1] << 16), ih[2] | (ih[3] << 16), ih[4] | (ih[5] << 16),
+                    ih[6] | (ih[7] << 16));
+  o[3] = make_uint4(il[0] | (il[1] << 16), il[2] | (il[3] << 16), il[4] | (il[5] << 16),
+                    il[6] | (il[7] << 16));
+}
+
+// LDS tile: [plane 4][row 64][chunk 4] of uint4 (8 bf16); chunk position swizzled by row.
+__device__ __forceinline__ int xoff(int plane, int row, int chunk) {
+  return (plane * 64 + row) * 4 + (chunk ^ ((row >> 2) & 3));
+}
+
+// One thread's share of an operand tile: 8 consecutive k values of one row (row = the M
+// index of op(A) or the N index of op(B)); KCONTIG: k is the contiguous storage direction.
+template <bool KCONTIG, bool CONJ>
+__device__ __forceinline__ void xload(const float2* P, long ld, int row0, int k0, int nrow, int K,
+                                      int t, float2 (&v)[8], int& row, int& chunk) {
+  if (KCONTIG) {  // element (r, k) at P[k + r ld]: four threads cover the 32 k of a row
+    row = t >> 2;
+    chunk = t & 3;
+  } else {        // element (r, k) at P[r + k ld]: lanes run along the rows
+    row = t & 63;
+    chunk = t >> 6;
+  }
+  const int gr = row0 + row;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int gk = k0 + chunk * 8 + e;
+    float2 x = make_float2(0.f, 0.f);
+    if (gr < nrow && gk < K) x = KCONTIG ? P[gk + (long)gr * ld] : P[gr + (long)gk * ld];
+    if (CONJ) x.y = -x.y;
+    v[e] = x;
+  }
+}
+
+template <int OPA, int OPB>
+__device__ __forceinline__ void gemmx_tile(const Args<float2>& a, int prob, int b1, int b2, int i0,
+                                           int j0, uint4* As, uint4* Bs) {
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int M = a.M, N = a.N;
+  int K = a.K;
+  const long lda = a.lda[prob], ldb = a.ldb[prob], ldc = a.ldc[prob];
+  const float2* A = a.A[prob] + b2 * a.sA2;
+  const float2* B = a.B[prob] + b2 * a.sB2;
+  float2* C = a.C[prob] + b1 * a.sC1 + b2 * a.sC2;
+  if (a.splitk == 0) {
+    A += b1 * a.sA1;
+    B += b1 * a.sB1;
+  } else {
+    const long kb = (long)b1 * a.splitk;
+    K = (K - kb < a.splitk) ? (int)(K - kb) : a.splitk;
+    A += (OPA == OP_N) ? kb * lda : kb;
+    B += (OPB == OP_N) ? kb : kb * ldb;
+  }
+  constexpr bool AK = (OPA != OP_N), BK_ = (OPB == OP_N);  // k contiguous in storage
+  constexpr int TILE = 4 * 64 * 4;                          // uint4 per operand tile
+
+  f4 acc_rr[2][2], acc_ii[2][2], acc_im[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      acc_rr[p][q] = f4{0, 0, 0, 0};
+      acc_ii[p][q] = f4{0, 0, 0, 0};
+      acc_im[p][q] = f4{0, 0, 0, 0};
+    }
+
+  float2 pa[8], pb[8], qa[8], qb[8];
+  int ra_row, ra_ch, rb_row, rb_ch;
+#define FEAST_XLOAD(KT, VA, VB)                                                          \
+  {                                                                                      \
+    xload<AK, OPA == OP_C>(A, lda, i0, (KT) * XBK, M, K, t, VA, ra_row, ra_ch);          \
+    xload<BK_, OPB == OP_C>(B, ldb, j0, (KT) * XBK, N, K, t, VB, rb_row, rb_ch);         \
+  }
+#define FEAST_XSTORE(BUF, VA, VB)                                                        \
+  {                                                                                      \
+    uint4 oa[4], ob[4];                                                                  \
+    split8(VA, oa);                                                                      \
+    split8(VB, ob);                                                                      \
+    uint4* sa = As + (BUF) * TILE;                                                       \
+    uint4* sb = Bs + (BUF) * TILE;                                                       \
+    _Pragma("unroll") for (int pl = 0; pl < 4; ++pl) {                                   \
+      sa[xoff(pl, ra_row, ra_ch)] = oa[pl];                                              \
+      sb[xoff(pl, rb_row, rb_ch)] = ob[pl];                                              \
+    }                                                                                    \
+  }
+#define FEAST_XCOMPUTE(BUF)                                                              \
+  {                                                                                      \
+    const uint4* sa = As + (BUF) * TILE;                                                 \
+    const uint4* sb = Bs + (BUF) * TILE;                                                 \
+    const int ch = lane >> 4;                                                            \
+    bf16x8 fa[2][4], fb[2][4];                                                           \
+    _Pragma("unroll") for (int q = 0; q < 2; ++q)                                        \
+      _Pragma("unroll") for (int pl = 0; pl < 4; ++pl) {                                 \
+        uint4 x = sa[xoff(pl, wm * 32 + q * 16 + (lane & 15), ch)];                      \
+        uint4 y = sb[xoff(pl, wn * 32 + q * 16 + (lane & 15), ch)];                      \
+        fa[q][pl] = __builtin_bit_cast(bf16x8, x);                                       \
+        fb[q][pl] = __builtin_bit_cast(bf16x8, y);                                       \
+      }                                                                                  \
+    _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                                     \
+      _Pragma("unroll") for (int nb = 0; nb < 2; ++nb) {                                 \
+        f4 rr = acc_rr[mb][nb], ii = acc_ii[mb][nb], im = acc_im[mb][nb];                \
+        rr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[nb][0], fa[mb][0], rr, 0, 0, 0); \
+        ii = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[nb][2], fa[mb][2], ii, 0, 0, 0); \
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[nb][2], fa[mb][0], im, 0, 0, 0); \
+        rr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[nb][0], fa[mb][1], rr, 0, 0, 0); \
+        ii = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[nb][2], fa[mb][3], ii, 0, 0, 0); \
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[nb][2], fa[mb][1], im, 0, 0, 0); \
+        rr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[nb][1], fa[mb][0], rr, 0, 0, 0); \
+        ii = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[nb][3], fa[mb][2], ii, 0, 0, 0); \
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[nb][3], fa[mb][0], im, 0, 0, 0); \
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[nb][0], fa[mb][2], im, 0, 0, 0); \
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[nb][0], fa[mb][3], im, 0, 0, 0); \
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[nb][1], fa[mb][2], im, 0, 0, 0); \
+        acc_rr[mb][nb] = rr;                                                             \
+        acc_ii[mb][nb] = ii;                                                             \
+        acc_im[mb][nb] = im;                                                             \
+      }                                                                                  \
+  }
+
+  // prefetch distance two, as in gemm_tile
+  const int nkt = (K + XBK - 1) / XBK;
+  if (nkt > 0) {
+    FEAST_XLOAD(0, pa, pb)
+    FEAST_XSTORE(0, pa, pb)
+  }
+  if (nkt > 1) FEAST_XLOAD(1, qa, qb)
+  __syncthreads();
+  for (int kt = 0; kt < nkt; kt += 2) {
+    if (kt + 2 < nkt) FEAST_XLOAD(kt + 2, pa, pb)
+    FEAST_XCOMPUTE(0)
+    if (kt + 1 < nkt) FEAST_XSTORE(1, qa, qb)
+    __syncthreads();
+    if (kt + 1 >= nkt) break;
+    if (kt + 3 < nkt) FEAST_XLOAD(kt + 3, qa, qb)
+    FEAST_XCOMPUTE(1)
+    if (kt + 2 < nkt) FEAST_XSTORE(0, pa, pb)
+    __syncthreads();
+  }
+#undef FEAST_XLOAD
+#undef FEAST_XSTORE
+#undef FEAST_XCOMPUTE
+
+  const float2 alpha = a.alpha, beta = a.beta;
+  const bool beta_zero = (beta.x == 0.f && beta.y == 0.f);
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int i = i0 + wm * 32 + mb * 16 + (lane & 15);
+        int j = j0 + wn * 32 + nb * 16 + 4 * (lane >> 4) + v;
+        if (i < M && j < N) {
+          float re = acc_rr[mb][nb][v] - acc_ii[mb][nb][v], im = acc_im[mb][nb][v];
+          float2 out;
+          out.x = alpha.x * re - alpha.y * im;
+          out.y = alpha.x * im + alpha.y * re;
+          if (!beta_zero) {
+            float2 c = C[i + (long)j * ldc];
+            out.x += beta.x * c.x - beta.y * c.y;
+            out.y += beta.x * c.y + beta.y * c.x;
+          }
+          C[i + (long)j * ldc] = out;
+        }
+      }
+}
+
+template <int OPA0, int OPA1, int OPB>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void gemmx_kernel(
+    const Args<float2> a) {
+  __shared__ uint4 As[2 * 4 * 64 * 4];
+  __shared__ uint4 Bs[2 * 4 * 64 * 4];
+  const long per = (long)a.tilesM * a.tilesN;
+  const long total = (long)gridDim.x * gridDim.y * gridDim.z;
+  const long L = blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * blockIdx.z);
+  const int x = (int)(L & 7);
+  long start = 0;
+  for (int q = 0; q < x; ++q) start += (total - q + 7) / 8;
+  const long g = start + (L >> 3);
+  const int tile = (int)(g % per);
+  long rest = g / per;
+  const int b1 = (int)(rest % a.n1);
+  rest /= a.n1;
+  const int b2 = (int)(rest % a.n2);
+  const int prob = (int)(rest / a.n2);
+  const int i0 = (tile / a.tilesN) * BM, j0 = (tile % a.tilesN) * BN;
+  if constexpr (OPA0 == OPA1) {
+    gemmx_tile<OPA0, OPB>(a, prob, b1, b2, i0, j0, As, Bs);
+  } else {
+    if (prob == 0) gemmx_tile<OPA0, OPB>(a, 0, b1, b2, i0, j0, As, Bs);
+    else gemmx_tile<OPA1, OPB>(a, 1, b1, b2, i0, j0, As, Bs);
+  }
+}
+
+void dispatchx(hipStream_t s, const int* opA, int nprob, int opB, const Args<float2>& a) {
+  GemmProfiler* prof = g_gemm_prof;
+  const double flops = 8.0 * a.M * a.N * (double)(a.K > 0 ? a.K : 0) *
+                       (a.splitk > 0 ? 1.0 : (double)a.n1) * a.n2 * nprob;
+  const int o0 = opA[0], o1 = (nprob == 2) ? opA[1] : opA[0];
+  bool done = false;
+  dim3 grid(a.tilesM * a.tilesN, a.n1, a.n2 * nprob);
+  if (prof) prof->begin(s);
+#define FEAST_GX(x, y, b)                                                         \
+  if (!done && o0 == x && o1 == y && opB == b) {                                  \
+    hipLaunchKernelGGL((gemmx_kernel<x, y, b>), grid, dim3(NT), 0, s, a);         \
+    done = true;                                                                  \
+  }
+  FEAST_GX(OP_N, OP_N, OP_N) FEAST_GX(OP_N, OP_N, OP_T) FEAST_GX(OP_N, OP_N, OP_C)
+  FEAST_GX(OP_T, OP_T, OP_N) FEAST_GX(OP_T, OP_T, OP_T) FEAST_GX(OP_T, OP_T, OP_C)
+  FEAST_GX(OP_C, OP_C, OP_N) FEAST_GX(OP_C, OP_C, OP_T) FEAST_GX(OP_C, OP_C, OP_C)
+  FEAST_GX(OP_N, OP_C, OP_N)
+#undef FEAST_GX
+  if (!done) throw HipError{hipErrorInvalidValue, "gemm bf16x3: unsupported op combination"};
+  FEAST_LAUNCH_CHECK();
+  if (prof) prof->end(s, flops);
+}
+
 template <typename v2>
 Args<v2> make_args(int M, int N, int K, v2 alpha, v2 beta, const Batch& bt) {
   Args<v2> a;
@@ -336,6 +591,12 @@ void gemm1(hipStream_t s, int opA, int opB, int M, int N, int K, typename CT<T>:
   a.ldb[0] = a.ldb[1] = ldb;
   a.ldc[0] = a.ldc[1] = ldc;
   int ops[1] = {opA};
+  if constexpr (sizeof(T) == 4) {
+    if (g_split_bf16) {
+      dispatchx(s, ops, 1, opB, a);
+      return;
+    }
+  }
   dispatch<T>(s, ops, 1, opB, a);
 }
 
@@ -355,6 +616,12 @@ void gemm2(hipStream_t s, int opA0, int opA1, int opB, int M, int N, int K,
     a.ldc[p] = ldc[p];
   }
   int ops[2] = {opA0, opA1};
+  if constexpr (sizeof(T) == 4) {
+    if (g_split_bf16) {
+      dispatchx(s, ops, 2, opB, a);
+      return;
+    }
+  }
   dispatch<T>(s, ops, 2, opB, a);
 }
 

@@ -18,7 +18,7 @@ extern "C" int feast_kern_gemm(int prec, int opA, int opB, int M, int N, int K,
                                const double* alpha, const void* A, long lda, const void* B,
                                long ldb, const double* beta, void* C, long ldc,
                                void* hip_stream) {
-  if (prec != 0 && prec != 1) return -1;
+  if (prec < 0 || prec > 2) return -1;
   if (opA < 0 || opA > 2) return -2;
   if (opB < 0 || opB > 2) return -3;
   if (M < 0) return -4;
@@ -37,9 +37,11 @@ extern "C" int feast_kern_gemm(int prec, int opA, int opB, int M, int N, int K,
     if (prec == 0)
       zgemm(s, opA, opB, M, N, K, zmake(alpha[0], alpha[1]), (const zd*)A, lda, (const zd*)B, ldb,
             zmake(beta[0], beta[1]), (zd*)C, ldc);
-    else
+    else {
+      SplitBf16Scope split(prec == 2);
       cgemm(s, opA, opB, M, N, K, make_float2((float)alpha[0], (float)alpha[1]), (const zf*)A,
             lda, (const zf*)B, ldb, make_float2((float)beta[0], (float)beta[1]), (zf*)C, ldc);
+    }
   } catch (const HipError&) {
     return -101;
   }
@@ -48,7 +50,7 @@ extern "C" int feast_kern_gemm(int prec, int opA, int opB, int M, int N, int K,
 
 extern "C" int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, const double* z,
                              void* LU, int* perm, int* np_out, void* hip_stream) {
-  if (prec != 0 && prec != 1) return -1;
+  if (prec < 0 || prec > 2) return -1;
   if (n < 1) return -4;
   if (!A) return -2;
   if (lda < n) return -3;
@@ -71,6 +73,7 @@ extern "C" int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, co
       shift_matrices(s, A, lda, 0, n, np, zdev, nc, (zd*)LU);
       lu_factor_f64(s, (zd*)LU, np, nc, w);
     } else {
+      SplitBf16Scope split(prec == 2);
       shift_matrices_f32(s, A, lda, 0, n, np, zdev, nc, (zf*)LU);
       lu_factor_f32(s, (zf*)LU, np, nc, w);
     }

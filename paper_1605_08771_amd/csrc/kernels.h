@@ -22,6 +22,15 @@ struct GemmProfiler {
 };
 extern thread_local GemmProfiler* g_gemm_prof;
 
+// When set (per thread), complex FP32 products (cgemm, cgemm_pair) run as bf16x3: each FP32
+// operand split into bf16 hi + lo, three bf16 matrix-core products with FP32 accumulation.
+extern thread_local bool g_split_bf16;
+struct SplitBf16Scope {
+  bool saved;
+  explicit SplitBf16Scope(bool on) : saved(g_split_bf16) { g_split_bf16 = on; }
+  ~SplitBf16Scope() { g_split_bf16 = saved; }
+};
+
 // C = alpha op(A) op(B) + beta C (column-major, complex; FP64 or FP32 matrix cores).
 void zgemm(hipStream_t s, int opA, int opB, int M, int N, int K, zd alpha, const zd* A, long lda,
            const zd* B, long ldb, zd beta, zd* C, long ldc, const Batch& bt = Batch());
@@ -111,8 +120,11 @@ void reduce_partials_hermitian(hipStream_t s, const zd* part, int nparts, int m,
 void cholesky_upper(hipStream_t s, zd* G, int m, int ldg, int* flag, zd* tmp);
 // Rinv = R^{-1} for upper triangular R (m x m); Rinv must be zeroed by the call.
 void upper_inverse(hipStream_t s, const zd* R, int m, int ldr, zd* Rinv, int ldi, zd* tmp);
-// Cyclic parallel-order Jacobi on the Hermitian m x m matrix H (ld = m, destroyed).
-// A rotation is skipped when |h_pq| <= max(1e-17 sqrt(|h_pp h_qq|), eps ||H||_F).
+// Cyclic two-sided Jacobi on the Hermitian m x m matrix H (ld = m, not modified) in a
+// block-pair parallel ordering (blocks of 16 indices; per outer round each pair of blocks
+// runs one inner sweep in LDS, then the round's block rotations are applied to the rest).
+// A rotation is skipped when |h_pq| <= max(1e-17 sqrt(|h_pp h_qq|), eps ||H||_F); a sweep
+// ends the iteration when no off-diagonal entry exceeds max(1e-17 sqrt(|h_pp h_qq|), 4 eps ||H||_F).
 // Returns sweeps used (host sync per sweep) or -1.  d (device, mp) eigenvalues unsorted,
 // V (device, mp x mp, ld mp) eigenvectors; work: jacobi_work(mp) complex.
 // One sweep is recorded as a HIP graph (rounds, then a fill kernel and the check: no memset
@@ -127,14 +139,15 @@ struct JacobiGraph {
   const void* flag = nullptr;
   ~JacobiGraph();
 };
-// mp = padded order (even, >= m; rows/columns beyond m are decoupled and sort last).
+// mp = padded order (a multiple of 32, >= m; rows/columns beyond m are decoupled and sort
+// last).
 int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* dflag,
                 int max_sweeps, JacobiGraph* cache, int mp);
-inline int jacobi_order(int m) { return m + (m & 1); }
+inline int jacobi_order(int m) { return (m + 31) / 32 * 32; }
 // Complex entries of jacobi_eigh's work array at padded order mp.
-inline size_t jacobi_work(int mp) { return 3 * (size_t)mp * mp + 40; }
-// A padded order on a coarse grid, so that recorded sweeps are reused across nearby sizes.
-inline int jacobi_order_quantized(int m) { return m <= 64 ? jacobi_order(m) : (m + 31) / 32 * 32; }
+inline size_t jacobi_work(int mp) { return (size_t)mp * mp + 32 * (size_t)mp + 40; }
+// Padded order used by callers that record sweeps for several nearby sizes.
+inline int jacobi_order_quantized(int m) { return jacobi_order(m); }
 // Stable ascending sort of d; Wout = V[:, order] (first m columns), lam = d[order].
 void sort_eigen(hipStream_t s, const double* d, const zd* V, int m, int mp, double* lam, zd* W,
                 int* rank);

@@ -1,7 +1,7 @@
 // Rayleigh-Ritz building blocks (Appendix, FEAST step 2; residuals of step 3):
 //   Cholesky-QR orthonormalisation of the filtered block (G = Q^H Q = R^H R, Q <- Q R^{-1}),
-//   parallel-order two-sided Jacobi for the m0 x m0 reduced matrix, eigenpair sort, and the
-//   residual norms ||A x_k - lambda_k x_k||.
+//   block-pair parallel-order two-sided Jacobi for the m0 x m0 reduced matrix, eigenpair sort,
+//   and the residual norms ||A x_k - lambda_k x_k||.
 #include "common.h"
 #include "kernels.h"
 
@@ -143,28 +143,43 @@ struct Rot {
   zd e;  // e^{-i phi}, phi = arg(h_pq)
 };
 
+// 1/d for finite d != 0: the hardware estimate refined by two Newton steps (each squares the
+// relative error), so the result is within a few ulp.
+__device__ inline double rcp_acc(double d) {
+  double x = __builtin_amdgcn_rcp(d);
+  x = fma(x, fma(-d, x, 1.0), x);
+  x = fma(x, fma(-d, x, 1.0), x);
+  return x;
+}
+
+// The rotation G = [[c, s], [-s e, c e]] that zeroes h_pq of the 2 x 2 Hermitian block
+// [[hpp, hpq], [conj(hpq), hqq]] (t = s / c, the smaller root of t^2 + 2 tau t - 1 = 0 with
+// tau = (hqq - hpp) / (2 |hpq|)); c = (1 + t^2)^{-1/2}, s = t c, e = conj(hpq) / |hpq|.
 // A rotation is skipped when |h_pq| <= max(1e-17 sqrt(|h_pp h_qq|), tol), tol = eps ||H||_F:
 // forming the reduced matrix already perturbs every entry by about eps ||H||, so rotating
-// smaller entries only chases rounding noise.
-__device__ inline Rot make_rot(const zd* __restrict__ H, int mp, int p, int q, double tol) {
+// smaller entries only chases rounding noise.  The tests are taken on squares and the
+// quotients through reciprocal square roots, which keeps the latency of the serial part of a
+// round short; every quantity stays within a few ulp, so G is unitary to a few ulp.
+__device__ inline Rot make_rot(double hpp, double hqq, zd hpq, double tol) {
   Rot r;
-  zd hpq = H[p + (long)q * mp];
-  double hpp = H[p + (long)p * mp].x, hqq = H[q + (long)q * mp].x;
-  double a = sqrt(hpq.x * hpq.x + hpq.y * hpq.y);
-  r.a = a;
-  r.active = !(a == 0.0 || a <= 1e-17 * sqrt(fabs(hpp * hqq)) || a <= tol);
+  const double a2 = hpq.x * hpq.x + hpq.y * hpq.y;
+  r.active = !(a2 == 0.0 || a2 <= 1e-34 * fabs(hpp * hqq) || a2 <= tol * tol);
   if (!r.active) {
+    r.a = sqrt(a2);
     r.c = 1;
     r.s = 0;
     r.t = 0;
     r.e = zmake(1, 0);
     return r;
   }
-  r.e = zmake(hpq.x / a, -hpq.y / a);
-  double tau = (hqq - hpp) / (2.0 * a);
-  double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  const double ra = rsqrt(a2);
+  r.a = a2 * ra;
+  r.e = zmake(hpq.x * ra, -hpq.y * ra);
+  const double tau = 0.5 * (hqq - hpp) * ra;
+  const double u = fma(tau, tau, 1.0);
+  const double tt = copysign(rcp_acc(fabs(tau) + u * rsqrt(u)), tau);
   r.t = tt;
-  r.c = 1.0 / sqrt(1.0 + tt * tt);
+  r.c = rsqrt(fma(tt, tt, 1.0));
   r.s = tt * r.c;
   return r;
 }
@@ -177,62 +192,151 @@ __device__ inline void pair_of(int a, int t, int mp, int& p, int& q) {
   q = x < y ? y : x;
 }
 
-__global__ __launch_bounds__(256) void jacobi_round_kernel(const zd* __restrict__ Hin,
-                                                           zd* __restrict__ Hout,
-                                                           const zd* __restrict__ Vin,
-                                                           zd* __restrict__ Vout, int mp,
-                                                           int round,
+// Block-pair ordering.  The mp indices form nb = mp / JB blocks of JB; an outer round pairs
+// the blocks by the same round-robin ordering (nb / 2 disjoint pairs P = I u J of JP = 2 JB
+// indices), and for each pair one workgroup runs parallel rounds of plane rotations over the
+// JP x JP diagonal tile H[P, P] in LDS, accumulating them into the unitary U_P.  A second
+// kernel then applies the outer round's block-diagonal transformation to the rest:
+// H[P, Q] <- U_P^H H[P, Q] U_Q (P != Q) and V[:, Q] <- V[:, Q] U_Q.  nb - 1 outer rounds are one
+// sweep, in which every index pair (p, q) is rotated once (pairs inside a block in the first
+// outer round, cross pairs when their blocks meet), as in the cyclic element ordering, but
+// with nb - 1 dependent launch pairs instead of mp - 1.
+constexpr int JB = 16;
+constexpr int JP = 2 * JB;
+
+// Global index of local index l (0..JP-1) of block pair (I, J).
+__device__ inline int pair_index(int l, int I, int J) { return l < JB ? I * JB + l : J * JB + l - JB; }
+
+// Outer round 0 of a sweep runs the full inner sweep (all JP (JP - 1) / 2 local pairs, so every
+// within-block pair is rotated once per sweep); later outer rounds rotate only the JB^2
+// cross pairs (p in I, q in J), in JB rounds pairing I[i] with J[(i + k) mod JB].
+__global__ __launch_bounds__(256) void jacobi_inner_kernel(zd* __restrict__ H, int mp, int round,
+                                                           zd* __restrict__ Ubuf,
                                                            const double* __restrict__ tolp) {
-  const int half = mp / 2;
+  __shared__ zd Hs[JP][JP + 1];
+  __shared__ zd Us[JP][JP + 1];
+  __shared__ double rc[JB], rsn[JB], rt[JB], ra[JB];
+  __shared__ zd re[JB];
+  __shared__ int rp[JB], rq[JB], ract[JB];
+  const int t = threadIdx.x;
+  const int nb = mp / JB;
+  int I, J;
+  pair_of(blockIdx.x, round, nb, I, J);
   const double tol = tolp[0];
-  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  long nA = (long)half * half;
-  if (idx < nA) {
-    int a = (int)(idx % half), b = (int)(idx / half);
-    int pa, qa, pb, qb;
-    pair_of(a, round, mp, pa, qa);
-    pair_of(b, round, mp, pb, qb);
-    Rot ra = make_rot(Hin, mp, pa, qa, tol);
-    Rot rb = (a == b) ? ra : make_rot(Hin, mp, pb, qb, tol);
-    zd b00 = Hin[pa + (long)pb * mp], b01 = Hin[pa + (long)qb * mp];
-    zd b10 = Hin[qa + (long)pb * mp], b11 = Hin[qa + (long)qb * mp];
-    // G = [[c, s], [-s e, c e]];  Y = G_a^H B
-    zd ga11 = zmake(ra.c, 0), ga12 = zmake(ra.s, 0);
-    zd ga21 = zscale(ra.e, -ra.s), ga22 = zscale(ra.e, ra.c);
-    zd y00 = zadd(zmul(zconj(ga11), b00), zmul(zconj(ga21), b10));
-    zd y01 = zadd(zmul(zconj(ga11), b01), zmul(zconj(ga21), b11));
-    zd y10 = zadd(zmul(zconj(ga12), b00), zmul(zconj(ga22), b10));
-    zd y11 = zadd(zmul(zconj(ga12), b01), zmul(zconj(ga22), b11));
-    zd gb11 = zmake(rb.c, 0), gb12 = zmake(rb.s, 0);
-    zd gb21 = zscale(rb.e, -rb.s), gb22 = zscale(rb.e, rb.c);
-    zd x00 = zadd(zmul(y00, gb11), zmul(y01, gb21));
-    zd x01 = zadd(zmul(y00, gb12), zmul(y01, gb22));
-    zd x10 = zadd(zmul(y10, gb11), zmul(y11, gb21));
-    zd x11 = zadd(zmul(y10, gb12), zmul(y11, gb22));
-    if (a == b && ra.active) {
-      x00 = zmake(Hin[pa + (long)pa * mp].x - ra.t * ra.a, 0);
-      x11 = zmake(Hin[qa + (long)qa * mp].x + ra.t * ra.a, 0);
-      x01 = zmake(0, 0);
-      x10 = zmake(0, 0);
+  for (int e = t; e < JP * JP; e += 256) {
+    int r = e % JP, c = e / JP;
+    Hs[r][c] = H[pair_index(r, I, J) + (long)pair_index(c, I, J) * mp];
+    Us[r][c] = zmake(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  const bool full = (round == 0);
+  const int nrounds = full ? JP - 1 : JB;
+  for (int it = 0; it < nrounds; ++it) {
+    if (t < JB) {
+      int p, q;
+      if (full) {
+        pair_of(t, it, JP, p, q);
+      } else {
+        p = t;
+        q = JB + (t + it) % JB;
+      }
+      Rot r = make_rot(Hs[p][p].x, Hs[q][q].x, Hs[p][q], tol);
+      rc[t] = r.c;
+      rsn[t] = r.s;
+      rt[t] = r.t;
+      ra[t] = r.a;
+      re[t] = r.e;
+      rp[t] = p;
+      rq[t] = q;
+      ract[t] = r.active;
     }
-    Hout[pa + (long)pb * mp] = x00;
-    Hout[pa + (long)qb * mp] = x01;
-    Hout[qa + (long)pb * mp] = x10;
-    Hout[qa + (long)qb * mp] = x11;
-    return;
+    __syncthreads();
+    {  // H <- G^H H G on the 2 x 2 sub-blocks (rotation pairs a, b): each entry once
+      const int a = t % JB, b = t / JB;
+      const int pa = rp[a], qa = rq[a], pb = rp[b], qb = rq[b];
+      zd b00 = Hs[pa][pb], b01 = Hs[pa][qb], b10 = Hs[qa][pb], b11 = Hs[qa][qb];
+      zd ga11 = zmake(rc[a], 0), ga12 = zmake(rsn[a], 0);
+      zd ga21 = zscale(re[a], -rsn[a]), ga22 = zscale(re[a], rc[a]);
+      zd y00 = zadd(zmul(zconj(ga11), b00), zmul(zconj(ga21), b10));
+      zd y01 = zadd(zmul(zconj(ga11), b01), zmul(zconj(ga21), b11));
+      zd y10 = zadd(zmul(zconj(ga12), b00), zmul(zconj(ga22), b10));
+      zd y11 = zadd(zmul(zconj(ga12), b01), zmul(zconj(ga22), b11));
+      zd gb11 = zmake(rc[b], 0), gb12 = zmake(rsn[b], 0);
+      zd gb21 = zscale(re[b], -rsn[b]), gb22 = zscale(re[b], rc[b]);
+      zd x00 = zadd(zmul(y00, gb11), zmul(y01, gb21));
+      zd x01 = zadd(zmul(y00, gb12), zmul(y01, gb22));
+      zd x10 = zadd(zmul(y10, gb11), zmul(y11, gb21));
+      zd x11 = zadd(zmul(y10, gb12), zmul(y11, gb22));
+      if (a == b && ract[a]) {
+        x00 = zmake(b00.x - rt[a] * ra[a], 0);
+        x11 = zmake(b11.x + rt[a] * ra[a], 0);
+        x01 = zmake(0, 0);
+        x10 = zmake(0, 0);
+      }
+      Hs[pa][pb] = x00;
+      Hs[pa][qb] = x01;
+      Hs[qa][pb] = x10;
+      Hs[qa][qb] = x11;
+    }
+    for (int e = t; e < JP * JB; e += 256) {  // U <- U G: row i, rotation b
+      const int i = e % JP, b = e / JP;
+      const int pb = rp[b], qb = rq[b];
+      zd gb11 = zmake(rc[b], 0), gb12 = zmake(rsn[b], 0);
+      zd gb21 = zscale(re[b], -rsn[b]), gb22 = zscale(re[b], rc[b]);
+      zd u0 = Us[i][pb], u1 = Us[i][qb];
+      Us[i][pb] = zadd(zmul(u0, gb11), zmul(u1, gb21));
+      Us[i][qb] = zadd(zmul(u0, gb12), zmul(u1, gb22));
+    }
+    __syncthreads();
   }
-  idx -= nA;
-  if (idx < (long)mp * half) {
-    int i = (int)(idx % mp), b = (int)(idx / mp);
-    int pb, qb;
-    pair_of(b, round, mp, pb, qb);
-    Rot rb = make_rot(Hin, mp, pb, qb, tol);
-    zd gb11 = zmake(rb.c, 0), gb12 = zmake(rb.s, 0);
-    zd gb21 = zscale(rb.e, -rb.s), gb22 = zscale(rb.e, rb.c);
-    zd v0 = Vin[i + (long)pb * mp], v1 = Vin[i + (long)qb * mp];
-    Vout[i + (long)pb * mp] = zadd(zmul(v0, gb11), zmul(v1, gb21));
-    Vout[i + (long)qb * mp] = zadd(zmul(v0, gb12), zmul(v1, gb22));
+  zd* U = Ubuf + (long)blockIdx.x * JP * JP;
+  for (int e = t; e < JP * JP; e += 256) {
+    int r = e % JP, c = e / JP;
+    H[pair_index(r, I, J) + (long)pair_index(c, I, J) * mp] = Hs[r][c];
+    U[e] = Us[r][c];
   }
+}
+
+// grid (npair, npair + mp / JP), 1024 threads (one output entry each).  y < npair: H tiles
+// P = y < Q = x: X = U_P^H H[P, Q] U_Q is written to H[P, Q] and X^H to H[Q, P] (the
+// transformed matrix stays exactly Hermitian; blocks with y >= x return at once).
+// y >= npair: V rows JP (y - npair) .. + JP - 1 against column pair Q = x.
+__global__ __launch_bounds__(1024) void jacobi_apply_kernel(zd* __restrict__ H, zd* __restrict__ V,
+                                                            int mp, int round,
+                                                            const zd* __restrict__ Ubuf) {
+  __shared__ zd Ts[JP][JP + 1];
+  __shared__ zd Uq[JP][JP + 1];
+  __shared__ zd Up[JP][JP + 1];
+  const int t = threadIdx.x;
+  const int nb = mp / JB, npair = nb / 2;
+  const int x = blockIdx.x, y = blockIdx.y;
+  const bool isH = y < npair;
+  if (isH && y >= x) return;  // diagonal tiles: inner kernel; lower tiles: mirrored below
+  int Iq, Jq, Ip = 0, Jp = 0;
+  pair_of(x, round, nb, Iq, Jq);
+  if (isH) pair_of(y, round, nb, Ip, Jp);
+  zd* M = isH ? H : V;
+  const int r0 = (y - npair) * JP;
+  const int c = t % JP, r = t / JP;
+  const int gc = pair_index(c, Iq, Jq);
+  const int gr = isH ? pair_index(r, Ip, Jp) : r0 + r;
+  Ts[r][c] = M[gr + (long)gc * mp];
+  Uq[r][c] = Ubuf[(long)x * JP * JP + r + c * JP];
+  if (isH) Up[r][c] = Ubuf[(long)y * JP * JP + r + c * JP];
+  __syncthreads();
+  zd acc = zmake(0, 0);
+#pragma unroll 8
+  for (int j = 0; j < JP; ++j) acc = zadd(acc, zmul(Ts[r][j], Uq[j][c]));
+  if (isH) {
+    __syncthreads();
+    Ts[r][c] = acc;
+    __syncthreads();
+    acc = zmake(0, 0);
+#pragma unroll 8
+    for (int j = 0; j < JP; ++j) acc = zadd(acc, zmul(zconj(Up[j][r]), Ts[j][c]));
+    H[gc + (long)gr * mp] = zconj(acc);
+  }
+  M[gr + (long)gc * mp] = acc;
 }
 
 __global__ void jacobi_check_kernel(const zd* __restrict__ H, int mp, const double* __restrict__ tolp,
@@ -244,10 +348,14 @@ __global__ void jacobi_check_kernel(const zd* __restrict__ H, int mp, const doub
   zd hpq = H[p + (long)q * mp];
   double a = sqrt(hpq.x * hpq.x + hpq.y * hpq.y);
   double hpp = H[p + (long)p * mp].x, hqq = H[q + (long)q * mp].x;
-  if (!(a == 0.0 || a <= 1e-17 * sqrt(fabs(hpp * hqq)) || a <= tolp[0])) atomicOr(flag, 1);
+  if (!(a == 0.0 || a <= 1e-17 * sqrt(fabs(hpp * hqq)) || a <= tolp[1])) atomicOr(flag, 1);
 }
 
-// tol = eps ||H||_F over the m x m input, in two deterministic stages (64 partial sums).
+// tol[0] = eps ||H||_F (rotation floor) and tol[1] = 4 eps ||H||_F (convergence test) over the
+// m x m input, in two deterministic stages (64 partial sums).  Each outer round transforms
+// every entry by 32-term block products, which leaves rounding noise of about eps ||H|| in the
+// off-diagonal part: a sweep still rotates entries down to that level, but convergence is
+// declared once none exceeds a few times it, which the noise cannot keep from happening.
 __global__ __launch_bounds__(256) void fro_partial_kernel(const zd* __restrict__ H, long count,
                                                           double* __restrict__ part) {
   __shared__ double sh[256];
@@ -270,6 +378,7 @@ __global__ void fro_final_kernel(const double* __restrict__ part, int nparts, do
     double s = 0;
     for (int i = 0; i < nparts; ++i) s += part[i];
     tol[0] = 2.220446049250313e-16 * sqrt(s);
+    tol[1] = 4.0 * tol[0];
   }
 }
 
@@ -484,33 +593,19 @@ void upper_inverse(hipStream_t s, const zd* R, int m, int ldr, zd* Rinv, int ldi
 }
 
 __global__ void zero_int_kernel(int* p) { p[0] = 0; }
-__global__ void copy_pair_kernel(const zd* __restrict__ a, zd* __restrict__ b, const zd* __restrict__ c,
-                                 zd* __restrict__ d, long count) {
-  long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (idx < count) {
-    b[idx] = a[idx];
-    d[idx] = c[idx];
-  }
-}
-
-// One sweep (mp - 1 rounds, ending on the buffers it started from) followed by the
-// convergence check, either launched directly or recorded into a graph by stream capture.
-static void jacobi_sweep_launches(hipStream_t s, zd* A0, zd* A1, zd* V0, zd* V1, int mp, int* dflag,
+// One sweep (nb - 1 outer rounds of an inner kernel and an apply kernel, in place) followed
+// by the convergence check, either launched directly or recorded into a graph by stream
+// capture.
+static void jacobi_sweep_launches(hipStream_t s, zd* A, zd* V, zd* Ubuf, int mp, int* dflag,
                                   const double* tolp) {
-  const long nthreads = (long)(mp / 2) * (mp / 2) + (long)mp * (mp / 2);
-  zd *Ain = A0, *Aout = A1, *Vin = V0, *Vout = V1;
-  for (int r = 0; r < mp - 1; ++r) {
-    hipLaunchKernelGGL(jacobi_round_kernel, grid1(nthreads), dim3(256), 0, s, Ain, Aout, Vin, Vout,
-                       mp, r, tolp);
-    std::swap(Ain, Aout);
-    std::swap(Vin, Vout);
-  }
-  if (Ain != A0) {  // odd round count: bring the result back to the starting buffers
-    hipLaunchKernelGGL(copy_pair_kernel, grid1((long)mp * mp), dim3(256), 0, s, Ain, A0, Vin, V0,
-                       (long)mp * mp);
+  const int nb = mp / JB, npair = nb / 2;
+  for (int r = 0; r < nb - 1; ++r) {
+    hipLaunchKernelGGL(jacobi_inner_kernel, dim3(npair), dim3(256), 0, s, A, mp, r, Ubuf, tolp);
+    hipLaunchKernelGGL(jacobi_apply_kernel, dim3(npair, npair + mp / JP), dim3(1024), 0, s, A, V,
+                       mp, r, (const zd*)Ubuf);
   }
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, dflag);
-  hipLaunchKernelGGL(jacobi_check_kernel, grid1((long)mp * mp), dim3(256), 0, s, A0, mp, tolp,
+  hipLaunchKernelGGL(jacobi_check_kernel, grid1((long)mp * mp), dim3(256), 0, s, A, mp, tolp,
                      dflag);
 }
 
@@ -521,23 +616,18 @@ JacobiGraph::~JacobiGraph() {
 
 int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* dflag,
                 int max_sweeps, JacobiGraph* cache, int mp) {
-  // work: 3 mp^2 + 40 complex (A ping, A pong, V pong; then 64 partial sums and tol as
-  // doubles); V is mp x mp.
-  if (mp < jacobi_order(m) || (mp & 1)) mp = jacobi_order(m);
+  // work: jacobi_work(mp) complex: the working matrix (mp^2), the outer round's block-pair
+  // unitaries (mp / JP of JP x JP), then 64 partial sums and tol as doubles; V is mp x mp.
+  if (mp < jacobi_order(m) || mp % JP)
+    throw HipError{hipErrorInvalidValue, "jacobi_eigh: padded order must be a multiple of 32 >= m"};
   zd* A0 = work;
-  zd* A1 = work + (long)mp * mp;
-  zd* V1 = work + 2L * mp * mp;
-  double* dwork = (double*)(work + 3L * mp * mp);
+  zd* Ubuf = work + (long)mp * mp;
+  double* dwork = (double*)(Ubuf + (long)mp * JP);
   double* tolp = dwork + 64;
   hipLaunchKernelGGL(jacobi_init_kernel, grid1((long)mp * mp), dim3(256), 0, s, H, m, mp, A0, V);
   hipLaunchKernelGGL(fro_partial_kernel, dim3(64), dim3(256), 0, s, H, (long)m * m, dwork);
   hipLaunchKernelGGL(fro_final_kernel, dim3(1), dim3(64), 0, s, dwork, 64, tolp);
   FEAST_LAUNCH_CHECK();
-  if (mp < 2) {
-    hipLaunchKernelGGL(diag_kernel, dim3(1), dim3(64), 0, s, A0, mp, d);
-    FEAST_LAUNCH_CHECK();
-    return 0;
-  }
   hipGraphExec_t exec = nullptr;
   if (cache && s) {  // the legacy null stream cannot be captured
     if (!(cache->exec && cache->mp == mp && cache->A0 == A0 && cache->V == V &&
@@ -547,7 +637,7 @@ int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* df
       cache->exec = cache->graph = nullptr;
       hipGraph_t g = nullptr;
       FEAST_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      jacobi_sweep_launches(s, A0, A1, V, V1, mp, dflag, tolp);
+      jacobi_sweep_launches(s, A0, V, Ubuf, mp, dflag, tolp);
       FEAST_HIP(hipStreamEndCapture(s, &g));
       hipGraphExec_t ge = nullptr;
       FEAST_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
@@ -564,7 +654,7 @@ int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* df
   bool converged = false;
   for (; sweeps < max_sweeps && !converged; ++sweeps) {
     if (exec) FEAST_HIP(hipGraphLaunch(exec, s));
-    else jacobi_sweep_launches(s, A0, A1, V, V1, mp, dflag, tolp);
+    else jacobi_sweep_launches(s, A0, V, Ubuf, mp, dflag, tolp);
     FEAST_LAUNCH_CHECK();
     int h = 0;
     FEAST_HIP(hipMemcpyAsync(&h, dflag, sizeof(int), hipMemcpyDeviceToHost, s));

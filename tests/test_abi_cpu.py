@@ -129,7 +129,8 @@ def test_solve_argument_checks():
     assert call(emax=-2.0) == -7
     assert call(opts=None) == -8
     for bad in (dict(n_c=0), dict(m0=0), dict(m0=11), dict(max_iter=0), dict(tol=0.0),
-                dict(prec=9), dict(prec=1, refine_max=-1), dict(method=3), dict(method=-1),
+                dict(prec=9), dict(prec=3), dict(prec=1, refine_max=-1), dict(prec=2, refine_max=-1),
+                dict(method=3), dict(method=-1),
                 dict(method=1, expand=0), dict(method=2, expand=0), dict(method=1, expand=3),
                 dict(method=2, expand=3)):
         o = fm.FeastOpts(n_c=8, m0=4, max_iter=10, refine_max=2, tol=1e-12, anorm=1.0, prec=0,

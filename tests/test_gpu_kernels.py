@@ -1,5 +1,6 @@
 """Kernel-level parity of the HIP building blocks against plain fp64 references on the host:
-the matrix-core complex GEMM (all op combinations, ragged shapes), the batched partial-pivot
+the matrix-core complex GEMM (all op combinations, ragged shapes; FP64, FP32 and bf16x3
+products), the batched partial-pivot
 LU of the shifted matrices, and the Jacobi reduced eigensolver."""
 import numpy as np
 import pytest
@@ -72,6 +73,60 @@ def test_cgemm_fp32(fe, opA, opB):
     assert np.abs(got - ref).max() <= 2e-5 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("opA", [0, 1, 2])
+@pytest.mark.parametrize("opB", [0, 1, 2])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (130, 77, 70), (65, 129, 0), (200, 31, 257)])
+def test_cgemm_bf16x3(fe, opA, opB, shape):
+    """bf16x3 products of complex64 operands against the exact product of the same operands.
+    With bf16 (8 significant bits, unit roundoff 2^-8) hi = RN(x), lo = RN(x - hi):
+    |x - hi - lo| <= 2^-16 |x|, and dropping lo_a lo_b adds at most 2^-16 |a||b|, so a real
+    product errs by at most ~3 2^-16 |a||b|; FP32 accumulation adds K 2^-24 sum |a||b|.  A
+    complex entry therefore errs by at most (3 2^-16 + K 2^-23) sum_k 2 |a_ik| |b_kj|.  A
+    dropped cross term (error ~2^-9 per product) exceeds this bound for these K."""
+    import torch
+    M, N, K = shape
+    rng = np.random.default_rng(M * 1000 + N * 10 + K + 7 * opA + opB + 5)
+    A = _crand(rng, M, K) if opA == 0 else _crand(rng, K, M)
+    B = _crand(rng, K, N) if opB == 0 else _crand(rng, N, K)
+    C = _crand(rng, M, N)
+    A = A.astype(np.complex64).astype(np.complex128)
+    B = B.astype(np.complex64).astype(np.complex128)
+    C = C.astype(np.complex64).astype(np.complex128)
+    alpha, beta = 0.75 - 0.25j, -1.0 + 0.5j
+    oA, oB = OPS[opA](A), OPS[opB](B)
+    ref = alpha * oA @ oB + beta * C
+    dA, dB, dC = (_dev(x, torch.complex64) for x in (A, B, C))
+    st = fe.gemm(opA, opB, dA, dB, dC, alpha, beta, M=M, N=N, K=K, split_bf16=True)
+    torch.cuda.synchronize()
+    assert st == 0
+    got = dC.cpu().numpy().astype(np.complex128)
+    bound = (3 * 2.0**-16 + K * 2.0**-23) * 2 * np.abs(alpha) * (np.abs(oA) @ np.abs(oB))
+    bound += 4 * 2.0**-24 * (np.abs(ref) + np.abs(beta * C)) + 1e-30
+    assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / bound)
+
+
+def test_cgemm_bf16x3_beats_bf16(fe):
+    """The lo parts matter: the bf16x3 error is far below a product of bf16-rounded operands."""
+    import torch
+    rng = np.random.default_rng(21)
+    M, N, K = 256, 128, 512
+    A = _crand(rng, M, K).astype(np.complex64).astype(np.complex128)
+    B = _crand(rng, K, N).astype(np.complex64).astype(np.complex128)
+    ref = A @ B
+    dA, dB = _dev(A, torch.complex64), _dev(B, torch.complex64)
+    dC = _dev(np.zeros((M, N)), torch.complex64)
+    assert fe.gemm(0, 0, dA, dB, dC, 1.0, 0.0, split_bf16=True) == 0
+    torch.cuda.synchronize()
+    err = np.abs(dC.cpu().numpy().astype(np.complex128) - ref).max()
+
+    def bf16(x):  # round to nearest even at 8 significant bits
+        return torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+
+    err_bf16 = np.abs((bf16(A.real) + 1j * bf16(A.imag)) @ (bf16(B.real) + 1j * bf16(B.imag))
+                      - ref).max()
+    assert err < err_bf16 / 64, (err, err_bf16)
+
+
 def test_zgemm_beta_zero_ignores_nan(fe):
     import torch
     rng = np.random.default_rng(3)
@@ -83,7 +138,8 @@ def test_zgemm_beta_zero_ignores_nan(fe):
     np.testing.assert_allclose(dC.cpu().numpy(), A @ B, rtol=0, atol=1e-12)
 
 
-@pytest.mark.parametrize("n,prec", [(60, 0), (200, 0), (500, 0), (1030, 0), (300, 1)])
+@pytest.mark.parametrize("n,prec", [(60, 0), (200, 0), (500, 0), (1030, 0), (300, 1), (300, 2),
+                                    (1030, 2)])
 def test_batched_lu(fe, n, prec):
     """P_j (z_j I - A) = L_j U_j for every node, with |L| <= 1 (partial pivoting)."""
     import torch
@@ -97,7 +153,8 @@ def test_batched_lu(fe, n, prec):
     LU = LU.cpu().numpy().astype(np.complex128)
     perm = perm.cpu().numpy()
     np_ = LU.shape[1]
-    eps = np.finfo(np.float64 if prec == 0 else np.float32).eps
+    # prec 2: trailing updates as bf16x3 products, ~3 2^-16 relative per product term
+    eps = {0: np.finfo(np.float64).eps, 1: np.finfo(np.float32).eps, 2: 2.0**-16}[prec]
     for j, zj in enumerate(z):
         M = np.eye(np_, dtype=np.complex128)
         M[:n, :n] = zj * np.eye(n) - A
@@ -131,7 +188,10 @@ def test_jacobi_vs_lapack(fe, m):
 def test_jacobi_gram_spectrum(fe, m):
     """A Gram matrix B^H B whose eigenvalues fall from 1 to 1e-16 (the orthogonalization of
     the expanded subspaces): eigenvalues to 1e-13 ||G|| absolutely, and the eigenvectors of the
-    eigenvalues above 1e-8 span LAPACK's invariant subspace."""
+    eigenvalues above 1e-8 span LAPACK's invariant subspace to the Davis-Kahan bound: the
+    sweeps stop once every off-diagonal entry is below 4 eps ||G||_F, so the angle between the
+    computed and the exact invariant subspace is at most about that residual over the
+    eigenvalue gap at the cut (a factor 8 allows for the norm of the residual block)."""
     import torch
     from tests.pins import sin_theta_max
     rng = np.random.default_rng(m + 7)
@@ -147,10 +207,15 @@ def test_jacobi_gram_spectrum(fe, m):
     dr, Wr = np.linalg.eigh(G)
     np.testing.assert_allclose(d, dr, rtol=0, atol=1e-13)
     big = dr > 1e-8
-    assert sin_theta_max(Wr[:, big], W[:, d > 1e-8]) < 1e-6
-    # a graded spectrum takes ~3x the sweeps of a random one; each rotation is unitary to one
-    # rounding error, so orthonormality is held to a multiple of m eps
-    np.testing.assert_allclose(W.conj().T @ W, np.eye(m), rtol=0, atol=max(1e-13, 8 * m * 2.2e-16))
+    k = int(np.argmax(big))  # first eigenvalue above the cut (ascending order)
+    gap = dr[k] - dr[k - 1]
+    bound = 8 * 4 * 2.2e-16 * np.linalg.norm(G) / gap
+    assert sin_theta_max(Wr[:, big], W[:, d > 1e-8]) < bound
+    # a graded spectrum takes ~3x the sweeps of a random one; each plane rotation is unitary to
+    # one rounding error, and a sweep composes them into m / 16 - 1 block transforms of V, each
+    # a product of 31 rotations applied as 32-term sums, so orthonormality is held to a
+    # multiple of m eps
+    np.testing.assert_allclose(W.conj().T @ W, np.eye(m), rtol=0, atol=max(1e-13, 16 * m * 2.2e-16))
 
 
 def test_binding_refuses_real_input_to_complex_calls(fe):

@@ -210,9 +210,15 @@ def test_solve_spurious_pairs_vs_oracle(fe, orc):
 
 
 # ---------------------------------------------------------------- mixed precision (FP32 factors)
+# fp32: FP32 matrix-core products; bf16x3: the same FP32 factor storage and refinement with the
+# factorization's and the solves' matrix-core products split into bf16 hi + lo parts.
+MIXED = {"fp32": 1, "bf16x3": 2}
 @pytest.mark.parametrize("dtype,n,m0", [("r64", 500, 75), ("c128", 777, 40)])
-def test_filter_apply_mixed_vs_oracle(fe, orc, dtype, n, m0):
-    """FP32 factors + two FP64-residual refinement steps reach the FP64 filtered block."""
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+def test_filter_apply_mixed_vs_oracle(fe, orc, mode, dtype, n, m0):
+    """FP32 factors + FP64-residual refinement steps (two for fp32, four for bf16x3, whose
+    per-step contraction is ~kappa 2^-16 instead of ~kappa 2^-24) reach the FP64 filtered
+    block."""
     import torch
     import paper_1605_08771_amd as fm
     rng = gen.rng_for([32, n])
@@ -221,7 +227,7 @@ def test_filter_apply_mixed_vs_oracle(fe, orc, dtype, n, m0):
     p = gen.make_problem(lam, emin, emax, m0, 8, 1e-12, 10, dtype == "c128", rng)
     ref = orc.filter_apply(dtype, p.A, emin, emax, 8, p.X0)
     fe.invalidate()
-    st, Q = fe.filter_apply(_dev(p.A), _dev(p.X0), emin, emax, 8, prec=fm.FEAST_FP32_IR)
+    st, Q = fe.filter_apply(_dev(p.A), _dev(p.X0), emin, emax, 8, prec=MIXED[mode])
     torch.cuda.synchronize()
     fe.invalidate()
     assert st == 0
@@ -229,7 +235,8 @@ def test_filter_apply_mixed_vs_oracle(fe, orc, dtype, n, m0):
     assert err < 1e-11, err
 
 
-def test_solve_mixed_config1_vs_oracle(fe, orc):
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+def test_solve_mixed_config1_vs_oracle(fe, orc, mode):
     """Config 1 (real symmetric n = 500) with FP32 factors: FP64-accurate result."""
     import torch
     import paper_1605_08771_amd as fm
@@ -238,13 +245,14 @@ def test_solve_mixed_config1_vs_oracle(fe, orc):
                           p.X0)
     fe.invalidate()
     out = fe.solve(_dev(p.A), p.emin, p.emax, p.m0, n_c=p.n_c, tol=p.tol, max_iter=p.max_iter,
-                   anorm=p.anorm, X0=_dev(p.X0), prec=fm.FEAST_FP32_IR, refine_max=0)
+                   anorm=p.anorm, X0=_dev(p.X0), prec=MIXED[mode], refine_max=0)
     torch.cuda.synchronize()
     fe.invalidate()
     _check_solve(p, out, ref, "r64", accept=out["mu"] > 0.5)
 
 
-def test_solve_mixed_hard_case_vs_oracle(fe, orc):
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+def test_solve_mixed_hard_case_vs_oracle(fe, orc, mode):
     """Config-2 recipe at n = 600 with FP32 factors and the Ritz-seeded correction."""
     import torch
     import paper_1605_08771_amd as fm
@@ -252,13 +260,14 @@ def test_solve_mixed_hard_case_vs_oracle(fe, orc):
     ref = orc.feast_solve("c128", p.A, p.emin, p.emax, 8, p.m0, p.tol, 200, p.anorm, p.X0)
     fe.invalidate()
     out = fe.solve(_dev(p.A), p.emin, p.emax, p.m0, n_c=8, tol=p.tol, max_iter=200,
-                   anorm=p.anorm, X0=_dev(p.X0), prec=fm.FEAST_FP32_IR, refine_max=0)
+                   anorm=p.anorm, X0=_dev(p.X0), prec=MIXED[mode], refine_max=0)
     torch.cuda.synchronize()
     fe.invalidate()
     _check_solve(p, out, ref, "c128", accept=out["mu"] > 0.5)
 
 
-def test_solve_mixed_spurious_vs_oracle(fe, orc):
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+def test_solve_mixed_spurious_vs_oracle(fe, orc, mode):
     """Hard case with spurious Ritz values, FP32 factors: same eigenpairs as the FP64 oracle."""
     import torch
     import paper_1605_08771_amd as fm
@@ -268,7 +277,7 @@ def test_solve_mixed_spurious_vs_oracle(fe, orc):
                           spurious=True)
     fe.invalidate()
     out = fe.solve(_dev(p.A), p.emin, p.emax, p.m0, n_c=8, tol=1e-12, max_iter=150,
-                   anorm=p.anorm, X0=_dev(p.X0), spurious=True, prec=fm.FEAST_FP32_IR,
+                   anorm=p.anorm, X0=_dev(p.X0), spurious=True, prec=MIXED[mode],
                    refine_max=0)
     torch.cuda.synchronize()
     fe.invalidate()
