@@ -230,7 +230,7 @@ def main():
     if args.workload == "c4":
         return bench_batched(args, dev)
     p = make_problem(args, dev)
-    prec_name = args.prec or ("fp32ir" if args.workload == "c3" else "fp64")
+    prec_name = args.prec or ("fp32ir" if args.workload in ("c3", "c5") else "fp64")
     prec = PRECS[prec_name]
     A = p.A
     X0 = p.X0

@@ -137,6 +137,9 @@ struct JacobiGraph {
   const void* A0 = nullptr;
   const void* V = nullptr;
   const void* flag = nullptr;
+  JacobiGraph() = default;
+  JacobiGraph(const JacobiGraph&) = delete;
+  JacobiGraph& operator=(const JacobiGraph&) = delete;
   ~JacobiGraph();
 };
 // mp = padded order (a multiple of 32, >= m; rows/columns beyond m are decoupled and sort
