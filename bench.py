@@ -30,6 +30,10 @@ sys.path.insert(0, ROOT)
 METRIC = "FEAST time-to-solution (res≤1e-10‖A‖) + filter-apply TFLOP/s, mixed vs FP64"
 PEAK_FP64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix
 PEAK_FP32_MFMA = 157.3
+# bf16x3 products: three bf16 matrix-core products per FP32 one (dense bf16 peak 2.5 PFLOP/s)
+PEAK_BF16X3_MFMA = 2500.0 / 3
+PEAKS = {0: PEAK_FP64_MFMA, 1: PEAK_FP32_MFMA, 2: PEAK_BF16X3_MFMA}
+SWEEP_KERNEL = {0: "gemm_kernel<double>", 1: "gemm_kernel<float>", 2: "gemmx_kernel (bf16x3)"}
 PEAK_HBM = 8000.0      # GB/s
 PRECS = {"fp64": 0, "fp32ir": 1, "bf16x3ir": 2}
 
@@ -37,7 +41,7 @@ PRECS = {"fp64": 0, "fp32ir": 1, "bf16x3ir": 2}
 # HBM bytes per launch of the paired sweep GEMM on the default workload (FP64, n=8192), from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy of known size; valid only
 # while the sources of that kernel are the ones the counters were taken on.
-SWEEP_TRAFFIC = {"sources": "ba3005f81a9fd333", "bytes_per_launch": 8.601e8}
+SWEEP_TRAFFIC = {"sources": "97d8227c1d3cbf48", "bytes_per_launch": 8.599e8}
 
 
 def kernel_sources_hash():
@@ -160,7 +164,7 @@ def bench_batched(args, dev):
     log(f"[bench] c4: bad={bad} ok={ok} max|dlam|={err:.2e} iters min/med/max "
         f"{min(iters)}/{int(np.median(iters))}/{max(iters)} time/step {total / args.steps:.3f}s")
     alg = sum(o["iters"] * 8 * 2 * 8.0 * p.n * p.n * p.m0 for p, o in zip(probs, outs)) * args.steps
-    peak = PEAK_FP64_MFMA if prec == fm.FEAST_FP64 else PEAK_FP32_MFMA
+    peak = PEAKS[prec]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     seq = one(1)
@@ -296,7 +300,7 @@ def main():
     # read and written once per sweep
     alg_solve_bytes = n_filters * p.n_c * 2 * (16.0 * p.n * p.n + sides * 2 * 16.0 * p.n * p.m0)
     achieved = alg_solve / (solve["ms"] * 1e-3) / 1e12 if solve["ms"] > 0 else 0.0
-    peak = PEAK_FP64_MFMA if prec == fm.FEAST_FP64 else PEAK_FP32_MFMA
+    peak = PEAKS[prec]
     filt_ms = sum(ph["solve_ms"] + ph["accumulate_ms"] for ph in phases)
     alg_filter = alg_solve + n_filters * p.n_c * sides * 8.0 * p.n * p.m0
     filter_tflops = alg_filter / (filt_ms * 1e-3) / 1e12 if filt_ms > 0 else 0.0
@@ -393,7 +397,7 @@ def main():
             "n": p.n, "m0": p.m0, "n_c": p.n_c, "precision": prec_name, "tol": 1e-10,
         },
         "roofline": {
-            "kernel": "gemm_kernel<double> in the block triangular sweeps (Y and adjoint Y')",
+            "kernel": f"{SWEEP_KERNEL[prec]} in the block triangular sweeps (Y and adjoint Y')",
             "bound": "mfma",
             "achieved": round(achieved, 2),
             "peak": peak,

@@ -73,6 +73,29 @@ def test_cgemm_fp32(fe, opA, opB):
     assert np.abs(got - ref).max() <= 2e-5 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("opA,opB", [(0, 0), (1, 0), (2, 0), (0, 2), (0, 1)])
+def test_cgemm_fp32_large_ragged(fe, opA, opB):
+    """FP32 products over about 2000 output tiles (more than the chip holds at once, so the
+    XCD-aware tile order wraps): ragged M, N and K, op(A) and op(B) variants, alpha and beta,
+    against the FP32 error bound 4 K 2^-24 sum |a||b| + |beta c| terms."""
+    import torch
+    M, N, K = 8201, 1003, 45
+    rng = np.random.default_rng(17 + 3 * opA + opB)
+    A = _crand(rng, M, K) if opA == 0 else _crand(rng, K, M)
+    B = _crand(rng, K, N) if opB == 0 else _crand(rng, N, K)
+    C = _crand(rng, M, N)
+    A, B, C = (x.astype(np.complex64).astype(np.complex128) for x in (A, B, C))
+    alpha, beta = 0.5 + 0.25j, -0.75 + 0.5j
+    ref = alpha * OPS[opA](A) @ OPS[opB](B) + beta * C
+    dA, dB, dC = (_dev(x, torch.complex64) for x in (A, B, C))
+    assert fe.gemm(opA, opB, dA, dB, dC, alpha, beta, M=M, N=N, K=K) == 0
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy().astype(np.complex128)
+    bound = 4 * K * 2.0**-24 * (np.abs(alpha) * (np.abs(OPS[opA](A)) @ np.abs(OPS[opB](B)))
+                                + np.abs(beta * C))
+    assert np.all(np.abs(got - ref) <= bound + 1e-30), np.max(np.abs(got - ref) / bound)
+
+
 @pytest.mark.parametrize("opA", [0, 1, 2])
 @pytest.mark.parametrize("opB", [0, 1, 2])
 @pytest.mark.parametrize("shape", [(1, 1, 1), (130, 77, 70), (65, 129, 0), (200, 31, 257)])
