@@ -20,6 +20,7 @@ namespace feast {
 namespace {
 
 constexpr int NBP = 64;   // panel width
+constexpr int NSUB = 8;   // panels per outer panel (trailing updates contract over NSUB * NBP)
 constexpr int RPW = 256;  // rows per workgroup in the panel kernels
 
 template <typename T>
@@ -430,25 +431,34 @@ void lu_factor(hipStream_t s, typename V2<T>::t* M, int np, int nc, LuWork& w) {
                        np, kp, width, c0, c1);
     FEAST_LAUNCH_CHECK();
   };
-  // Outer panels of two 64-wide sub-panels: the trailing update then contracts over 128
-  // columns at once (half the read-modify-write traffic of two 64-deep updates).
-  for (int k = 0; k < np; k += 2 * NBP) {
-    const int w0 = (np - k < NBP) ? np - k : NBP;
-    const int w1 = (np - k - w0 < NBP) ? np - k - w0 : NBP;
-    factor_panel(k, w0);
-    if (w1 > 0) {  // bring sub-panel 1 up to date, then factor it
-      trsm(k, w0, k + w0, k + w0 + w1);
-      gemm_update<T>(s, M, np, nc, k + w0, np - k - w0, k + w0, w1, k, w0);
-      factor_panel(k + w0, w1);
+  // Outer panels of NSUB 64-wide sub-panels: the trailing update then contracts over
+  // NSUB * 64 columns at once (1 / NSUB of the read-modify-write traffic of 64-deep updates).
+  // Inside an outer panel the sub-panels are factored right-looking over the panel's own
+  // columns; the panel's block rows of U for the trailing columns follow by block forward
+  // substitution.
+  for (int k = 0; k < np; k += NSUB * NBP) {
+    int kw[NSUB];
+    int W = 0;
+    for (int q = 0; q < NSUB; ++q) {
+      kw[q] = std::max(0, std::min(NBP, np - k - W));
+      W += kw[q];
     }
-    const int c = k + w0 + w1;
-    if (c < np) {
-      trsm(k, w0, c, np);
-      if (w1 > 0) {
-        gemm_update<T>(s, M, np, nc, k + w0, w1, c, np - c, k, w0);
-        trsm(k + w0, w1, c, np);
+    for (int q = 0, kq = k; q < NSUB && kw[q] > 0; kq += kw[q], ++q) {
+      factor_panel(kq, kw[q]);
+      const int e = kq + kw[q];  // first column of the outer panel not yet factored
+      if (e < k + W) {
+        trsm(kq, kw[q], e, k + W);
+        gemm_update<T>(s, M, np, nc, e, np - e, e, k + W - e, kq, kw[q]);
       }
-      gemm_update<T>(s, M, np, nc, c, np - c, c, np - c, k, w0 + w1);
+    }
+    const int c = k + W;
+    if (c < np) {
+      for (int q = 0, kq = k; q < NSUB && kw[q] > 0; kq += kw[q], ++q) {
+        trsm(kq, kw[q], c, np);
+        const int e = kq + kw[q];
+        if (e < c) gemm_update<T>(s, M, np, nc, e, c - e, c, np - c, kq, kw[q]);
+      }
+      gemm_update<T>(s, M, np, nc, c, np - c, c, np - c, k, W);
     }
   }
   long tot = (long)np * nc;
