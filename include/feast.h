@@ -136,6 +136,9 @@ void feast_invalidate(feast_handle h);
  *   A: n x n (lda >= n); X: n x m0 (ldx >= n); Q: n x m0 output (ldq >= n), must not alias X.
  *   The n_c factorizations of z_j I - A are cached in h, keyed by (A pointer, n, lda, dtype,
  *   emin, emax, n_c, prec); call feast_invalidate after changing A in place.
+ * Mixed modes refine each system's solution (FP64 residuals X - (z_j I - A) Y, corrections
+ * through the low-precision factors) until the largest residual entry no longer drops below
+ * 0.9 of the previous one, at most 10 steps (FEAST_FP32_IR) or 30 (FEAST_BF16X3_IR).
  * Argument positions for negative codes: h=1 dt=2 n=3 A=4 lda=5 emin=6 emax=7 (needs
  * emin < emax) n_c=8 prec=9 X=10 ldx=11 m0=12 (1 <= m0 <= n) Q=13 ldq=14.
  * Positive returns: FEAST_ZERO_PIVOT, FEAST_NONFINITE. */

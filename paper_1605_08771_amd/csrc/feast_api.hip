@@ -65,9 +65,15 @@ void gauss_legendre_gw(int n, std::vector<double>& x, std::vector<double>& w) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Device buffer owned by a handle; grows on demand and is freed with the handle (every Buf
+// member, including those feast_destroy does not list, through this destructor).
 struct Buf {
   void* p = nullptr;
   size_t bytes = 0;
+  Buf() = default;
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  ~Buf() { release(); }
   template <typename T>
   T* get(size_t count) {
     size_t need = count * sizeof(T);
@@ -230,7 +236,7 @@ struct feast_ctx {
   Buf b_B, b_Z, b_Xc, b_Qc, b_X0c;
   // Rayleigh-Ritz
   Buf b_Q1, b_Q2, b_AQ, b_AX, b_G, b_part, b_Rinv, b_rrtmp, b_H, b_jac, b_V, b_d, b_lam, b_res,
-      b_rank, b_W, b_flag, b_diag, b_pow, b_mu, b_Reig, b_Y64, b_AY, b_rho;
+      b_rank, b_W, b_flag, b_diag, b_pow, b_mu, b_Reig, b_Y64, b_AY, b_rho, b_rmax;
   std::vector<double> mu;
   PhaseTimer timer;
   KernelProfiler prof;
@@ -398,11 +404,13 @@ struct RitzInfo {
 };
 
 // Q (n x m0 complex, ldq) = rho(A) X with X n x m0 complex (ldx).  Factors must be ready.
-// FP32_IR: with ritz, the Ritz-seeded correction; without, FP32 solves plus `refine` classic
-// refinement steps whose residuals X - (z I - A) Y are FP64 (A: complex n x n, lda).
+// Mixed modes: with ritz, the Ritz-seeded correction; without, low-precision solves plus
+// `refine` classic refinement steps whose residuals X - (z I - A) Y are FP64 (A: complex
+// n x n, lda).  adaptive: `refine` is a cap, and refinement stops once the largest residual
+// entry no longer falls below 0.9 of the previous one (it has reached its FP64 floor).
 int filter_core(feast_ctx* h, int dt, int n, int m0, const zd* X, long ldx, zd* Q, long ldq,
                 const zd* A = nullptr, long lda = 0, const RitzInfo* ritz = nullptr,
-                int refine = 0) {
+                int refine = 0, bool adaptive = false) {
   hipStream_t s = h->stream;
   const int np = h->f_np, nc = h->f_nc, nbt = h->f_nbt;
   const int sides = (dt == FEAST_C128) ? 2 : 1;
@@ -470,15 +478,26 @@ int filter_core(feast_ctx* h, int dt, int n, int m0, const zd* X, long ldx, zd* 
   zd* Y = h->b_Y64.get<zd>(blk);
   zd* AY = h->b_AY.get<zd>(blk);
   unpermute_to64(s, B32, pinv, n, np, m0, nc, sides, 0, Y);
+  unsigned long long* rmax = adaptive ? h->b_rmax.get<unsigned long long>(1) : nullptr;
+  double prev = INFINITY;
   for (int it = 0; it < refine; ++it) {
     hipEvent_t e0 = h->timer.mark(s);
     {
       ScopedProf sp(h->prof, K_REFINE);
       zgemm(s, OP_N, OP_N, n, nc * sides * m0, n, zmake(1, 0), A, lda, Y, np, zmake(0, 0), AY, np);
     }
-    refine_rhs(s, X, ldx, Y, AY, zdev, perm, n, np, m0, nc, sides, B32);
+    refine_rhs(s, X, ldx, Y, AY, zdev, perm, n, np, m0, nc, sides, B32, rmax);
     hipEvent_t e1 = h->timer.mark(s);
     h->timer.add(e0, e1, P_REFINE);
+    if (adaptive) {
+      unsigned long long bits = 0;
+      FEAST_HIP(hipMemcpyAsync(&bits, rmax, sizeof(bits), hipMemcpyDeviceToHost, s));
+      FEAST_HIP(hipStreamSynchronize(s));
+      double r;
+      std::memcpy(&r, &bits, sizeof(r));
+      if (!(r < 0.9 * prev)) break;  // stagnated at the FP64 floor (or not finite)
+      prev = r;
+    }
     sweep32();
     unpermute_to64(s, B32, pinv, n, np, m0, nc, sides, 1, Y);
   }
@@ -953,7 +972,7 @@ int feast_destroy(feast_handle h) {
                  &h->b_Q1, &h->b_Q2, &h->b_AQ, &h->b_AX, &h->b_G, &h->b_part, &h->b_Rinv,
                  &h->b_rrtmp, &h->b_H, &h->b_jac, &h->b_V, &h->b_d, &h->b_lam, &h->b_res,
                  &h->b_rank, &h->b_W, &h->b_flag, &h->b_diag, &h->b_pow, &h->b_mu,
-                 &h->b_Reig, &h->b_Y64, &h->b_AY, &h->b_rho};
+                 &h->b_Reig, &h->b_Y64, &h->b_AY, &h->b_rho, &h->b_rmax};
   for (Buf* b : bufs) b->release();
   if (h->own_stream) (void)hipStreamDestroy(h->stream);
   delete h;
@@ -1030,10 +1049,11 @@ int feast_filter_apply(feast_handle h, feast_dtype dt, int n, const void* A, int
     }
     long ldac = lda;
     const zd* Ac = (prec != FEAST_FP64) ? complex_A(h, dt, n, A, lda, &ldac) : nullptr;
-    // Classic refinement: each step contracts the error by ~kappa(z_j I - A) times the
-    // products' relative accuracy (2^-24 FP32, ~2^-16 bf16x3).
+    // Classic refinement until the FP64 residual stops shrinking: each step contracts the
+    // error by about kappa(z_j I - A) times the products' relative accuracy (2^-24 FP32,
+    // ~2^-16 bf16x3), so bf16x3 may need many more steps.
     st = filter_core(h, dt, n, m0, Xc, ldxc, Qc, ldqc, Ac, ldac, nullptr,
-                     prec == FEAST_BF16X3_IR ? 4 : 2);
+                     prec == FEAST_BF16X3_IR ? 30 : 10, true);
     if (st == 0 && dt == FEAST_R64) complex_to_real(s, Qc, n, (double*)Q, ldq, n, m0);
     hipEvent_t t1 = h->timer.mark(s);
     h->timer.add(t0, t1, P_TOTAL);

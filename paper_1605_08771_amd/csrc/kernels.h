@@ -109,8 +109,10 @@ void accumulate_mixed(hipStream_t s, const zd* X, long ldx, const double* rho, c
                       long ldq);
 void unpermute_to64(hipStream_t s, const zf* D, const int* pinv, int n, int np, int m0, int nc,
                     int sides, int add, zd* Y);
+// rmax (device, nullable): receives max |R| over all entries as the bits of a double.
 void refine_rhs(hipStream_t s, const zd* X, long ldx, const zd* Y, const zd* AY, const zd* z,
-                const int* perm, int n, int np, int m0, int nc, int sides, zf* B);
+                const int* perm, int n, int np, int m0, int nc, int sides, zf* B,
+                unsigned long long* rmax = nullptr);
 void accumulate_plain(hipStream_t s, const zd* Y, int n, int np, int m0, int nc, int sides,
                       const zd* omega, zd* Q, long ldq);
 

@@ -115,30 +115,47 @@ __global__ void unpermute_kernel(const zf* __restrict__ D, const int* __restrict
 
 // B32[j][s][r, c] = R[src, c] with R = X - zz Y + AY (FP64) at row src = perm_j[r] (side 0)
 // or r (side 1).  Y, AY: [nc][sides] blocks of np x m0 in original row order.
-__global__ void refine_rhs_kernel(const zd* __restrict__ X, long ldx, const zd* __restrict__ Y,
-                                  const zd* __restrict__ AY, const zd* __restrict__ z,
-                                  const int* __restrict__ perm, int n, int np, int m0, int nc,
-                                  int sides, zf* __restrict__ B) {
+// rmax (optional): the largest |R| entry over all systems, accumulated as the bit pattern of
+// a non-negative double (whose unsigned order is its numeric order); zeroed by the caller.
+__global__ __launch_bounds__(256) void refine_rhs_kernel(
+    const zd* __restrict__ X, long ldx, const zd* __restrict__ Y, const zd* __restrict__ AY,
+    const zd* __restrict__ z, const int* __restrict__ perm, int n, int np, int m0, int nc,
+    int sides, zf* __restrict__ B, unsigned long long* rmax) {
+  __shared__ double sm[256];
   long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   long per = (long)np * m0;
-  if (idx >= per * nc * sides) return;
-  long blk = idx / per, e = idx % per;
-  int node = (int)(blk / sides), side = (int)(blk % sides);
-  int r = (int)(e % np), c = (int)(e / np);
-  zf out = make_float2(0.f, 0.f);
-  if (r < n) {
-    int src = (side == 0) ? perm[(long)node * np + r] : r;
-    if (src < n) {
-      zd zz = z[node];
-      if (side == 1) zz.y = -zz.y;
-      long o = blk * per + src + (long)c * np;
-      zd y = Y[o];
-      zd v = zadd(zsub(X[src + (long)c * ldx], zmul(zz, y)), AY[o]);
-      out = make_float2((float)v.x, (float)v.y);
+  double mag = 0.0;
+  if (idx < per * nc * sides) {
+    long blk = idx / per, e = idx % per;
+    int node = (int)(blk / sides), side = (int)(blk % sides);
+    int r = (int)(e % np), c = (int)(e / np);
+    zf out = make_float2(0.f, 0.f);
+    if (r < n) {
+      int src = (side == 0) ? perm[(long)node * np + r] : r;
+      if (src < n) {
+        zd zz = z[node];
+        if (side == 1) zz.y = -zz.y;
+        long o = blk * per + src + (long)c * np;
+        zd y = Y[o];
+        zd v = zadd(zsub(X[src + (long)c * ldx], zmul(zz, y)), AY[o]);
+        out = make_float2((float)v.x, (float)v.y);
+        mag = sqrt(v.x * v.x + v.y * v.y);
+        if (!(mag <= 1.79e308)) mag = 1.79e308;  // non-finite: largest finite value
+      }
     }
+    B[idx] = out;
   }
-  B[idx] = out;
+  if (!rmax) return;  // uniform over the grid
+  sm[threadIdx.x] = mag;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(rmax, (unsigned long long)__double_as_longlong(sm[0]));
 }
+
+__global__ void zero_u64_kernel(unsigned long long* p) { p[0] = 0ull; }
 
 // Q = sum_j omega_j Y0_j + conj(omega_j) Y1_j (both in original row order), or 2 Re(.)
 __global__ void accumulate_plain_kernel(const zd* __restrict__ Y, int n, int np, int m0, int nc,
@@ -197,10 +214,15 @@ void unpermute_to64(hipStream_t s, const zf* D, const int* pinv, int n, int np, 
 }
 
 void refine_rhs(hipStream_t s, const zd* X, long ldx, const zd* Y, const zd* AY, const zd* z,
-                const int* perm, int n, int np, int m0, int nc, int sides, zf* B) {
+                const int* perm, int n, int np, int m0, int nc, int sides, zf* B,
+                unsigned long long* rmax) {
   long tot = (long)np * m0 * nc * sides;
+  if (rmax) {
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, rmax);
+    FEAST_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(refine_rhs_kernel, grid1(tot), dim3(256), 0, s, X, ldx, Y, AY, z, perm, n, np,
-                     m0, nc, sides, B);
+                     m0, nc, sides, B, rmax);
   FEAST_LAUNCH_CHECK();
 }
 

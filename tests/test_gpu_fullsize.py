@@ -1,0 +1,128 @@
+"""The HIP path at the full configuration sizes, in the launch configuration bench.py times
+(n = 8192, m0 = 300, n_c = 8 for the FEAST and XFEAST solves and the filter; n = 16384,
+m0 = 400, n_c = 16 for the mixed solve), checked where the oracle cannot follow (an FP64 CPU
+FEAST at n = 8192 takes hours):
+
+- the filtered block on sampled columns against its exact value for the construction
+  A = U diag(lam) U^H: rho(A) x = U diag(rho(lam)) U^H x with rho the closed form of the
+  quadrature filter (pinned against the oracle in test_oracle_pins.py), computed on the host
+  in FP64.  Bar 1e-10 relative: each shifted solve errs by about kappa(z_j I - A) times a
+  modest multiple of u, with kappa <= ||A|| / (r sin theta_min) ~ 3e2 for n_c = 8;
+- the converged eigenpairs against the construction: every eigenvalue inside I to
+  1e-10 ||A|| (the metric's threshold), residuals at most the tolerance, and the span of the
+  counted Ritz vectors against U[:, inside] within the Davis-Kahan bound
+  sin(theta_max) <= ||R||_2 / gap <= sqrt(m) max_k ||r_k|| / gap, gap being the distance
+  between the eigenvalues inside I and the rest of the spectrum (about 1e-4 here: the clusters
+  sit 5e-5 from each endpoint).  Run to the configuration's own tolerance 1e-12, FEAST must
+  also reach the stated target sin(theta_max) <= 1e-8."""
+import numpy as np
+import pytest
+
+from paper_1605_08771_amd import gen
+from tests.pins import orthonormal, rho_closed, sin_theta_max
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fe():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need the HIP device"
+    import paper_1605_08771_amd as fm
+    f = fm.Feast()
+    yield f
+    f.close()
+
+
+@pytest.fixture(scope="module")
+def c2():
+    import torch
+    p = gen.config2(device=torch.device("cuda"))
+    assert p.n == 8192 and p.m0 == 300 and p.n_c == 8
+    return p
+
+
+def _exact_filter_columns(p, cols):
+    """U diag(rho(lam)) U^H X0[:, cols] in FP64 on the host."""
+    U = p.U.cpu().numpy()
+    x = p.X0[:, cols].cpu().numpy()
+    rho = rho_closed(p.lam, p.emin, p.emax, p.n_c)
+    return U @ (rho[:, None] * (U.conj().T @ x))
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_c2_filter_sampled_columns_vs_exact(fe, c2, prec):
+    """FP64 (prec 0), and FP32 factors (1) or bf16x3 products (2) with FP64-residual
+    refinement run until the residual stops shrinking."""
+    import torch
+    fe.invalidate()
+    st, Q = fe.filter_apply(c2.A, c2.X0, c2.emin, c2.emax, c2.n_c, prec=prec)
+    torch.cuda.synchronize()
+    fe.invalidate()
+    assert st == 0
+    cols = [0, 77, 151, 299]
+    ref = _exact_filter_columns(c2, cols)
+    got = Q[:, cols].cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < 1e-10, err
+
+
+def _check_converged(p, out, tol, target=None):
+    lam, res, mu = out["lam"], out["res"], out.get("mu")
+    sel = (lam > p.emin) & (lam < p.emax)
+    if mu is not None:
+        sel &= mu > 0.5
+    inside = (p.lam > p.emin) & (p.lam < p.emax)
+    exact = np.sort(p.lam[inside])
+    assert out["status"] == 0, out["status"]
+    assert out["m"] == p.m_true and int(sel.sum()) == p.m_true
+    np.testing.assert_allclose(np.sort(lam[sel]), exact, rtol=0, atol=1e-10 * p.anorm)
+    assert np.max(res[sel]) <= tol
+    out_l = np.sort(p.lam[~inside])
+    gap = min(np.min(np.abs(exact[:, None] - out_l[None, np.searchsorted(out_l, p.emin) - 1:
+                                                      np.searchsorted(out_l, p.emax) + 1])),
+              np.inf)
+    bound = np.sqrt(p.m_true) * np.max(res[sel]) * p.anorm / gap
+    Uin = p.U[:, torch_index(np.flatnonzero(inside))].cpu().numpy()
+    X = out["X"].cpu().numpy()[:, sel]
+    angle = sin_theta_max(orthonormal(Uin), orthonormal(X))
+    assert angle <= bound, (angle, bound)
+    if target is not None:
+        assert angle <= target, angle
+
+
+def torch_index(idx):
+    import torch
+    return torch.from_numpy(np.asarray(idx, dtype=np.int64)).cuda()
+
+
+@pytest.mark.parametrize("prec,method,expand,tol", [(0, "feast", 1, 1e-10), (1, "feast", 1, 1e-10),
+                                                    (0, "xfeast", 2, 1e-10),
+                                                    (0, "feast", 1, 1e-12)])
+def test_c2_solve_full_size(fe, c2, prec, method, expand, tol):
+    """The bench's C2 solve (stop at 1e-10 ||A||, filter-value test on): FEAST in FP64 and
+    FP32+IR, XFEAST with two blocks; and FEAST in FP64 to the configuration's 1e-12."""
+    import torch
+    fe.invalidate()
+    out = fe.solve(c2.A, c2.emin, c2.emax, c2.m0, n_c=c2.n_c, tol=tol, max_iter=200,
+                   anorm=c2.anorm, X0=c2.X0, prec=prec, spurious=True, refine_max=0,
+                   method=method, expand=expand)
+    torch.cuda.synchronize()
+    fe.invalidate()
+    _check_converged(c2, out, tol, target=1e-8 if tol <= 1e-12 else None)
+
+
+def test_c3_mixed_solve_full_size(fe):
+    """Config 3 (n = 16384, m0 = 400, n_c = 16) with FP32 factors and FP64 refinement, to the
+    configuration's own tolerance 1e-12."""
+    import torch
+    p = gen.config3(device=torch.device("cuda"))
+    assert p.n == 16384 and p.m0 == 400 and p.n_c == 16
+    fe.invalidate()
+    out = fe.solve(p.A, p.emin, p.emax, p.m0, n_c=p.n_c, tol=p.tol, max_iter=p.max_iter,
+                   anorm=p.anorm, X0=p.X0, prec=1, spurious=True, refine_max=0)
+    torch.cuda.synchronize()
+    fe.invalidate()
+    _check_converged(p, out, p.tol, target=1e-8)
+    del p
+    torch.cuda.empty_cache()

@@ -216,9 +216,9 @@ MIXED = {"fp32": 1, "bf16x3": 2}
 @pytest.mark.parametrize("dtype,n,m0", [("r64", 500, 75), ("c128", 777, 40)])
 @pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
 def test_filter_apply_mixed_vs_oracle(fe, orc, mode, dtype, n, m0):
-    """FP32 factors + FP64-residual refinement steps (two for fp32, four for bf16x3, whose
-    per-step contraction is ~kappa 2^-16 instead of ~kappa 2^-24) reach the FP64 filtered
-    block."""
+    """FP32 factors + FP64-residual refinement steps, run until the residual stops shrinking
+    (bf16x3 contracts by ~kappa 2^-16 per step instead of ~kappa 2^-24), reach the FP64
+    filtered block."""
     import torch
     import paper_1605_08771_amd as fm
     rng = gen.rng_for([32, n])
