@@ -256,13 +256,6 @@ int fail_hip(feast_ctx* h, const HipError& e) {
   return FEAST_ERR_HIP;
 }
 
-int pick_nbt(int n) {
-  if (n >= 8192) return 512;
-  if (n >= 2048) return 256;
-  if (n >= 384) return 128;
-  return 64;
-}
-
 // Factorizations of z_j I - A for all nodes (cached).
 int ensure_factors(feast_ctx* h, int dt, int n, const void* A, int lda, double emin, double emax,
                    int nc, int prec, const void* B = nullptr, int ldb = 0) {
@@ -272,7 +265,7 @@ int ensure_factors(feast_ctx* h, int dt, int n, const void* A, int lda, double e
     return 0;
   h->f_valid = false;
   hipStream_t s = h->stream;
-  const int nbt = pick_nbt(n);
+  const int nbt = sweep_block(n);
   const int np = (n + nbt - 1) / nbt * nbt;
   // nodes and weights
   std::vector<double> x, w;

@@ -8,8 +8,8 @@
 using namespace feast;
 
 namespace {
-int pick_np(int n) {
-  int nbt = n >= 2048 ? 256 : (n >= 384 ? 128 : 64);
+int pick_np(int n) {  // the padding the solver uses (a multiple of the sweep block height)
+  const int nbt = sweep_block(n);
   return (n + nbt - 1) / nbt * nbt;
 }
 }  // namespace

@@ -87,6 +87,9 @@ void gather_rhs(hipStream_t s, const zd* X, long ldx, int n, int np, int m0, int
 void gather_rhs_f32(hipStream_t s, const zd* X, long ldx, int n, int np, int m0, int nc,
                     int sides, const int* perm, zf* B);
 
+// Height of the sweep blocks (and of the inverted diagonal blocks) for order n: the factors
+// are padded to a multiple of it.
+int sweep_block(int n);
 // Forward then backward block sweeps for all (node, side) systems.  B (input RHS, destroyed)
 // and Y (output) are [nc][sides] blocks of np x m0.
 void solve_sweeps_f64(hipStream_t s, const zd* LU, const zd* invL, const zd* invU, int np,

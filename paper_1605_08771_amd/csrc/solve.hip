@@ -317,6 +317,13 @@ void gather_rhs_f32(hipStream_t s, const zd* X, long ldx, int n, int np, int m0,
   FEAST_LAUNCH_CHECK();
 }
 
+int sweep_block(int n) {
+  if (n >= 8192) return 512;
+  if (n >= 2048) return 256;
+  if (n >= 384) return 128;
+  return 64;
+}
+
 void solve_sweeps_f64(hipStream_t s, const zd* LU, const zd* invL, const zd* invU, int np,
                       int nc, int nbt, int sides, int m0, zd* B, zd* Y) {
   sweeps<double>(s, LU, invL, invU, np, nc, nbt, sides, m0, B, Y);
