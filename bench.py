@@ -219,8 +219,9 @@ def main():
                     help="c2 eigenvectors: QR of a Gaussian matrix (default) or 8 dense "
                          "reflectors built without library factorizations (for counter runs)")
     ap.add_argument("--variants", default=None,
-                    help="comma list of method:s runs of the Sec. 2 variants reported beside "
-                         "FEAST (default for c2: rfeast:2,rfeast:3,xfeast:2,xfeast:3; '' = none)")
+                    help="comma list of method:s[:precision] runs of the Sec. 2 variants "
+                         "reported beside FEAST (default for c2: rfeast:2,rfeast:3,xfeast:2,"
+                         "xfeast:3,xfeast:2:fp32ir; '' = none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -274,9 +275,11 @@ def main():
     f.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    outs, phases = [], []
+    outs, phases, step_s = [], [], []
     for k in range(args.steps):
-        out = one(1e-10)
+        ts = time.perf_counter()
+        out = one(1e-10)  # returns after the solve's final stream sync (host outputs)
+        step_s.append(time.perf_counter() - ts)
         outs.append(out)
         phases.append(f.timings())
     torch.cuda.synchronize()
@@ -340,21 +343,24 @@ def main():
     variants = []
     vspec = args.variants
     if vspec is None:
-        vspec = "rfeast:2,rfeast:3,xfeast:2,xfeast:3" if args.workload == "c2" else ""
+        vspec = ("rfeast:2,rfeast:3,xfeast:2,xfeast:3,xfeast:2:fp32ir" if args.workload == "c2"
+                 else "")
     for item in [v for v in vspec.split(",") if v]:
-        meth, sx = item.split(":")
-        sx = int(sx)
-        one(1e-10, max_iter=2, method=meth, expand=sx)  # buffers and recorded sweeps
+        parts = item.split(":")  # method:expand[:precision]
+        meth, sx = parts[0], int(parts[1])
+        vprec_name = parts[2] if len(parts) > 2 else prec_name
+        vprec = PRECS[vprec_name]
+        one(1e-10, max_iter=2, pr=vprec, method=meth, expand=sx)  # buffers, recorded sweeps
         f.set_profiling(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ov = one(1e-10, method=meth, expand=sx)
+        ov = one(1e-10, pr=vprec, method=meth, expand=sx)
         torch.cuda.synchronize()
         tv = time.perf_counter() - t0
         eig = f.kernel_stats("eig")
         f.set_profiling(False)
         okv, errv, resv = check(ov, 1e-10)
-        rec = {"method": meth, "expand": sx, "precision": prec_name, "time_s": round(tv, 4),
+        rec = {"method": meth, "expand": sx, "precision": vprec_name, "time_s": round(tv, 4),
                "iterations": ov["iters"], "correct": okv, "max_eig_err": errv,
                "max_residual": resv,
                "phase_ms": {k: round(v, 2) for k, v in f.timings().items()},
@@ -414,6 +420,9 @@ def main():
         },
         "filter_apply_tflops": round(filter_tflops, 2),
         "iterations": iters,
+        "step_times_s": [round(x, 4) for x in step_s],
+        "step_time_median_s": round(float(np.median(step_s)), 4),
+        "step_time_min_s": round(float(np.min(step_s)), 4),
         "correct": all(c[0] for c in checks),
         "max_eig_err": max(c[1] for c in checks),
         "max_residual": max(c[2] for c in checks),
