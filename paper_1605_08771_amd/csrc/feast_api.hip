@@ -1398,7 +1398,7 @@ int feast_solve_batched(feast_handle h, feast_dtype dt, int nprob, const feast_p
           st = feast_solve(wh, dt, p.n, p.A, p.lda, p.emin, p.emax, &o, p.X0, p.X, p.ldx,
                            p.lambda, p.res, p.m, p.iters, nullptr);
         if (p.mu)
-          for (int k = 0; k < p.m0; ++k) p.mu[k] = k < (int)wh->mu.size() ? wh->mu[k] : 0.0;
+          for (int q = 0; q < p.m0; ++q) p.mu[q] = q < (int)wh->mu.size() ? wh->mu[q] : 0.0;
         if (p.status) *p.status = st;
       }
     };

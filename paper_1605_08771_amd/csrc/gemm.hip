@@ -161,7 +161,7 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
     FEAST_STORE_AB(0, A0, B0) FEAST_STORE_AB(1, A1, B1)                              \
     FEAST_STORE_AB(2, A2, B2) FEAST_STORE_AB(3, A3, B3)                              \
   }
-#define FEAST_COMPUTE(BUF)                                                           \
+#define FEAST_COMPUTE(BUF, CHK)                                                      \
   {                                                                                  \
     const int buf = (BUF);                                                           \
     _Pragma("unroll") for (int kk = 0; kk < BK / 4; ++kk) {                          \
@@ -173,23 +173,29 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
         fb[nb] = Bs[buf][kidx][wn * 32 + nb * 16 + (lane & 15)];                      \
       _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                               \
         _Pragma("unroll") for (int nb = 0; nb < 2; ++nb) {                           \
+          if ((CHK) && !live[mb][nb]) continue;                                      \
           accr[mb][nb] = mfma(fb[nb].x, fa[mb].x, accr[mb][nb]);                     \
           acci[mb][nb] = mfma(fb[nb].x, fa[mb].y, acci[mb][nb]);                     \
         }                                                                            \
       _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                               \
         _Pragma("unroll") for (int nb = 0; nb < 2; ++nb) {                           \
+          if ((CHK) && !live[mb][nb]) continue;                                      \
           accr[mb][nb] = mfma(-fb[nb].y, fa[mb].y, accr[mb][nb]);                    \
           acci[mb][nb] = mfma(fb[nb].y, fa[mb].x, acci[mb][nb]);                     \
         }                                                                            \
     }                                                                                \
   }
   accv accr[2][2], acci[2][2];
+  // A 16 x 16 output block that lies entirely past M or N has nothing to compute; the test
+  // is uniform over the wave, so skipping its MFMAs frees the matrix core for other waves.
+  bool live[2][2];
 #pragma unroll
   for (int p = 0; p < 2; ++p)
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       accr[p][q] = accv{T(0), T(0), T(0), T(0)};
       acci[p][q] = accv{T(0), T(0), T(0), T(0)};
+      live[p][q] = (i0 + wm * 32 + p * 16 < M) && (j0 + wn * 32 + q * 16 < N);
     }
 
   const int nkt = (K + BK - 1) / BK;
@@ -201,17 +207,28 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
   }
   if (nkt > 1) FEAST_LOAD_TILE_INTO(BK, qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3)
   __syncthreads();
-  for (int kt = 0; kt < nkt; kt += 2) {
-    if (kt + 2 < nkt) FEAST_LOAD_TILE_INTO((kt + 2) * BK, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)
-    FEAST_COMPUTE(0)
-    if (kt + 1 < nkt) FEAST_STORE_TILE_FROM(1, qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3)
-    __syncthreads();
-    if (kt + 1 >= nkt) break;
-    if (kt + 3 < nkt) FEAST_LOAD_TILE_INTO((kt + 3) * BK, qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3)
-    FEAST_COMPUTE(1)
-    if (kt + 2 < nkt) FEAST_STORE_TILE_FROM(0, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)
-    __syncthreads();
+#define FEAST_KLOOP(CHK)                                                             \
+  for (int kt = 0; kt < nkt; kt += 2) {                                              \
+    if (kt + 2 < nkt)                                                                \
+      FEAST_LOAD_TILE_INTO((kt + 2) * BK, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)    \
+    FEAST_COMPUTE(0, CHK)                                                            \
+    if (kt + 1 < nkt) FEAST_STORE_TILE_FROM(1, qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3) \
+    __syncthreads();                                                                 \
+    if (kt + 1 >= nkt) break;                                                        \
+    if (kt + 3 < nkt)                                                                \
+      FEAST_LOAD_TILE_INTO((kt + 3) * BK, qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3)    \
+    FEAST_COMPUTE(1, CHK)                                                            \
+    if (kt + 2 < nkt) FEAST_STORE_TILE_FROM(0, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3) \
+    __syncthreads();                                                                 \
   }
+  // The branch is uniform over the workgroup (it depends on the tile origin only), so both
+  // loops see the same barriers; only ragged edge tiles pay for the per-block tests.
+  if (i0 + BM <= M && j0 + BN <= N) {
+    FEAST_KLOOP(0)
+  } else {
+    FEAST_KLOOP(1)
+  }
+#undef FEAST_KLOOP
 #undef FEAST_LOAD_A
 #undef FEAST_LOAD_B
 #undef FEAST_LOAD_TILE_INTO
