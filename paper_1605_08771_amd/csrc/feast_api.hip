@@ -236,7 +236,7 @@ struct feast_ctx {
   Buf b_B, b_Z, b_Xc, b_Qc, b_X0c;
   // Rayleigh-Ritz
   Buf b_Q1, b_Q2, b_AQ, b_AX, b_G, b_part, b_Rinv, b_rrtmp, b_H, b_jac, b_V, b_d, b_lam, b_res,
-      b_rank, b_W, b_flag, b_diag, b_pow, b_mu, b_Reig, b_Y64, b_AY, b_rho, b_rmax;
+      b_rank, b_W, b_flag, b_diag, b_pow, b_mu, b_Reig, b_Y64, b_AY, b_rho, b_rmax, b_kpart;
   std::vector<double> mu;
   PhaseTimer timer;
   KernelProfiler prof;
@@ -501,6 +501,15 @@ int filter_core(feast_ctx* h, int dt, int n, int m0, const zd* X, long ldx, zd* 
   return 0;
 }
 
+// C = A B for a tall product (n x n times n x k, FP64 complex): K is cut into chunks whose
+// partial products are summed when that spreads the output tiles more evenly over the device.
+void tall_product(feast_ctx* h, int M, int N, int K, const zd* A, long lda, const zd* B,
+                  long ldb, zd* C, long ldc) {
+  const int nk = zgemm_kchunks(M, N, K);
+  zd* part = nk > 1 ? h->b_kpart.get<zd>((size_t)nk * M * N) : nullptr;
+  zgemm_nn_split(h->stream, M, N, K, A, lda, B, ldb, C, ldc, nk, part);
+}
+
 // Q <- Q R^{-1} with G = Q^H Q = R^H R; Q1 (nq x m0 zero-padded rows) -> Q2.
 // Returns 0, 1 on Cholesky breakdown.
 // G = Q1^H Q1, or Q1^H (B Q1) for a pencil (split-K products, Hermitian reduction).
@@ -512,7 +521,7 @@ void gram_matrix(feast_ctx* h, int n, int m0, const zd* Q1, const PencilB& pb, z
   const zd* R = Q1;
   if (pb.B) {
     zd* BQ = h->b_BQ.get<zd>((size_t)n * m0);
-    zgemm(s, OP_N, OP_N, n, m0, n, zmake(1, 0), pb.B, pb.ld, Q1, n, zmake(0, 0), BQ, n);
+    tall_product(h, n, m0, n, pb.B, pb.ld, Q1, n, BQ, n);
     R = BQ;
   }
   Batch b;
@@ -599,7 +608,7 @@ int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m
   }
   // Q1 orthonormal (B-orthonormal for a pencil).  A' = Q^H (A Q).
   zd* AQ = h->b_AQ.get<zd>((size_t)n * m0);
-  zgemm(s, OP_N, OP_N, n, m0, n, zmake(1, 0), A, lda, Q1, n, zmake(0, 0), AQ, n);
+  tall_product(h, n, m0, n, A, lda, Q1, n, AQ, n);
   const int nsplit = std::max(1, std::min(32, n / 256));
   const int kc = (n + nsplit - 1) / nsplit;
   zd* part = h->b_part.get<zd>((size_t)nsplit * m0 * m0);
@@ -632,7 +641,7 @@ int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m
   const zd* BX = Q2;  // B X (X itself when B = I)
   if (pb.B) {
     zd* bx = h->b_BX.get<zd>((size_t)n * m0);
-    zgemm(s, OP_N, OP_N, n, m0, n, zmake(1, 0), pb.B, pb.ld, Q2, n, zmake(0, 0), bx, n);
+    tall_product(h, n, m0, n, pb.B, pb.ld, Q2, n, bx, n);
     BX = bx;
   }
   double* res = h->b_res.get<double>(m0);
@@ -965,7 +974,7 @@ int feast_destroy(feast_handle h) {
                  &h->b_Q1, &h->b_Q2, &h->b_AQ, &h->b_AX, &h->b_G, &h->b_part, &h->b_Rinv,
                  &h->b_rrtmp, &h->b_H, &h->b_jac, &h->b_V, &h->b_d, &h->b_lam, &h->b_res,
                  &h->b_rank, &h->b_W, &h->b_flag, &h->b_diag, &h->b_pow, &h->b_mu,
-                 &h->b_Reig, &h->b_Y64, &h->b_AY, &h->b_rho, &h->b_rmax};
+                 &h->b_Reig, &h->b_Y64, &h->b_AY, &h->b_rho, &h->b_rmax, &h->b_kpart};
   for (Buf* b : bufs) b->release();
   if (h->own_stream) (void)hipStreamDestroy(h->stream);
   delete h;
@@ -1145,7 +1154,7 @@ int solve_impl(feast_handle h, feast_dtype dt, int n, const void* A, int lda, co
     // the filter's right-hand side for the block Xc: Xc itself, or B Xc for a pencil
     auto rhs = [&](const zd* Xc) -> const zd* {
       if (!B) return Xc;
-      zgemm(s, OP_N, OP_N, n, m0, n, zmake(1, 0), pb.B, pb.ld, Xc, n, zmake(0, 0), BXf, n);
+      tall_product(h, n, m0, n, pb.B, pb.ld, Xc, n, BXf, n);
       return BXf;
     };
     st = FEAST_NOT_CONVERGED;
@@ -1336,7 +1345,7 @@ int feast_filter_apply_gen(feast_handle h, feast_dtype dt, int n, const void* A,
     long ldbc = 0;
     const zd* Bc = complex_B(h, dt, n, B, ldb, &ldbc);
     zd* BX = h->b_BXf.get<zd>((size_t)n * m0);
-    zgemm(s, OP_N, OP_N, n, m0, n, zmake(1, 0), Bc, ldbc, Xc, ldxc, zmake(0, 0), BX, n);
+    tall_product(h, n, m0, n, Bc, ldbc, Xc, ldxc, BX, n);
     zd* Qc = (dt == FEAST_R64) ? h->b_Qc.get<zd>((size_t)n * m0) : (zd*)Q;
     long ldqc = (dt == FEAST_R64) ? n : ldq;
     st = filter_core(h, dt, n, m0, BX, n, Qc, ldqc);

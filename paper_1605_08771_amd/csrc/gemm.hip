@@ -25,6 +25,9 @@
 // Batching: two nested strided batch dimensions with their own element strides, and up to
 // two independent problems (own A/B/C pointers, leading dimensions and op(A)) with the same
 // M, N, K in one launch; split-K reductions are a batch dimension over K chunks.
+#include <algorithm>
+#include <atomic>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -652,6 +655,72 @@ void cgemm(hipStream_t s, int opA, int opB, int M, int N, int K, zf alpha, const
            const zf* B, long ldb, zf beta, zf* C, long ldc, const Batch& bt) {
   gemm1<float>(s, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
 }
+namespace {
+__global__ __launch_bounds__(256) void sum_partials_kernel(const zd* part, int nparts, int M,
+                                                           long len, zd* C, long ldc) {
+  const long i = blockIdx.x * 256L + threadIdx.x;
+  if (i >= len) return;
+  zd acc = part[i];
+  for (int p = 1; p < nparts; ++p) acc = zadd(acc, part[(long)p * len + i]);
+  C[(i % M) + (i / M) * ldc] = acc;
+}
+
+// Workgroups of the FP64 op(N, N) GEMM kernel resident on the current device at once.
+int zgemm_resident_tiles() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  FEAST_HIP(hipGetDevice(&dev));
+  std::atomic<int>* c = (dev >= 0 && dev < 64) ? &cache[dev] : nullptr;
+  if (c && c->load() > 0) return c->load();
+  int cus = 0, per_cu = 0;
+  FEAST_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  FEAST_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void*>(&gemm_kernel<double, OP_N, OP_N, OP_N>), NT, 0));
+  const int r = std::max(1, cus * std::max(1, per_cu));
+  if (c) c->store(r);
+  return r;
+}
+}  // namespace
+
+int zgemm_kchunks(int M, int N, int K) {
+  if (M <= 0 || N <= 0 || K < 512) return 1;
+  const long tiles = (long)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  const long slots = zgemm_resident_tiles();
+  // Cost model: rounds of resident workgroups times the K length each one runs.  A split
+  // is taken only when it saves at least 3 % (the partial sums cost a pass over C).
+  int best = 1;
+  double best_cost = (double)((tiles + slots - 1) / slots) * K;
+  for (int nk = 2; nk <= 8; ++nk) {
+    const int chunk = (K + nk - 1) / nk;
+    if (chunk < 256) break;
+    const double cost = (double)((tiles * nk + slots - 1) / slots) * chunk;
+    if (cost < 0.97 * best_cost) {
+      best = nk;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
+void zgemm_nn_split(hipStream_t s, int M, int N, int K, const zd* A, long lda, const zd* B,
+                    long ldb, zd* C, long ldc, int nchunk, zd* part) {
+  const zd one = zmake(1, 0), zero = zmake(0, 0);
+  if (nchunk <= 1) {
+    zgemm(s, OP_N, OP_N, M, N, K, one, A, lda, B, ldb, zero, C, ldc);
+    return;
+  }
+  if (M <= 0 || N <= 0) return;
+  Batch b;
+  b.n1 = nchunk;
+  b.splitk = (K + nchunk - 1) / nchunk;
+  b.sC1 = (long)M * N;
+  zgemm(s, OP_N, OP_N, M, N, K, one, A, lda, B, ldb, zero, part, M, b);
+  const long len = (long)M * N;
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s,
+                     part, nchunk, M, len, C, ldc);
+  FEAST_LAUNCH_CHECK();
+}
+
 void zgemm_pair(hipStream_t s, int opA0, int opA1, int opB, int M, int N, int K, zd alpha,
                 const zd* const A[2], const long lda[2], const zd* const B[2], const long ldb[2],
                 zd beta, zd* const C[2], const long ldc[2], const Batch& bt) {

@@ -37,6 +37,15 @@ void zgemm(hipStream_t s, int opA, int opB, int M, int N, int K, zd alpha, const
 void cgemm(hipStream_t s, int opA, int opB, int M, int N, int K, zf alpha, const zf* A, long lda,
            const zf* B, long ldb, zf beta, zf* C, long ldc, const Batch& bt = Batch());
 
+// K-chunk count for C = A B (FP64, op N/N; K = the inner length) that spreads the output
+// tiles of all chunks more evenly over the workgroups the device holds at once (1 = no
+// split; at most 8, chunks of at least 256).
+int zgemm_kchunks(int M, int N, int K);
+// C = A B (beta = 0).  nchunk > 1: partial products of K chunks into part
+// (nchunk * M * N elements, ld M), then summed into C in chunk order.
+void zgemm_nn_split(hipStream_t s, int M, int N, int K, const zd* A, long lda, const zd* B,
+                    long ldb, zd* C, long ldc, int nchunk, zd* part);
+
 // Two problems with equal M, N, K (own pointers, leading dimensions, op(A)) in one launch.
 void zgemm_pair(hipStream_t s, int opA0, int opA1, int opB, int M, int N, int K, zd alpha,
                 const zd* const A[2], const long lda[2], const zd* const B[2], const long ldb[2],

@@ -4,8 +4,10 @@
     python -m paper_1605_08771_amd.microbench jacobi --m 300 --kind random --reps 3
 
 `gemm` runs C = -op(A) op(B) + C through `feast_kern_gemm` (prec fp64, fp32 or bf16x3) on
-seeded Gaussian operands (one untimed call first, then `reps` timed ones; a counter run sees
-reps + 1 dispatches); `jacobi` runs `feast_kern_jacobi` on a seeded Hermitian matrix
+seeded Gaussian operands (one untimed call first, then `rounds` rounds of `reps` timed ones,
+the fastest round reported; a counter run with one round sees reps + 1 dispatches); with
+`--vendor` it also times the same product through torch.addmm (the ROCm BLAS libraries, fp64
+and fp32 only), alternating the two from round to round; `jacobi` runs `feast_kern_jacobi` on a seeded Hermitian matrix
 (random, or a Gram matrix with eigenvalues from 1 to 1e-16).  Each prints one line with the
 average time per call measured with HIP events on the library's stream.
 """
@@ -31,20 +33,39 @@ def _gemm(a):
     f = fm.Feast()
     s = f._stream
     split = a.prec == "bf16x3"
-    if f.gemm(a.opA, a.opB, A, B, C, -1.0, 1.0, M=M, N=N, K=K, split_bf16=split) != 0:
-        raise SystemExit("feast_kern_gemm failed")  # warm-up call (code load), not timed
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def ours():
+        st = f.gemm(a.opA, a.opB, A, B, C, -1.0, 1.0, M=M, N=N, K=K, split_bf16=split)
+        if st != 0:
+            raise SystemExit(f"feast_kern_gemm returned {st}")
+
+    def op(X, o):
+        return X if o == 0 else (X.mT if o == 1 else X.mH)
+
+    D = C.clone() if a.vendor and not split else None
+
+    def vendor():
+        torch.addmm(C, op(A, a.opA), op(B, a.opB), beta=1.0, alpha=-1.0, out=D)
+
+    runs = [("gemm", ours)] + ([("vendor torch.addmm", vendor)] if D is not None else [])
+    best = {}
     with torch.cuda.stream(s):
-        e0.record()
-        for _ in range(a.reps):
-            st = f.gemm(a.opA, a.opB, A, B, C, -1.0, 1.0, M=M, N=N, K=K, split_bf16=split)
-            if st != 0:
-                raise SystemExit(f"feast_kern_gemm returned {st}")
-        e1.record()
+        for _, fn in runs:
+            fn()  # warm-up call (code load), not timed
+        for r in range(a.rounds):
+            for name, fn in (runs if r % 2 == 0 else runs[::-1]):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(a.reps):
+                    fn()
+                e1.record()
+                e1.synchronize()
+                best[name] = min(best.get(name, 1e30), e0.elapsed_time(e1) / a.reps)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / a.reps
-    print(f"gemm {a.prec} opA={a.opA} opB={a.opB} M={M} N={N} K={K}: {ms * 1e3:.1f} us/call, "
-          f"{8.0 * M * N * K / (ms * 1e-3) / 1e12:.2f} TFLOP/s", flush=True)
+    for name, _ in runs:
+        ms = best[name]
+        print(f"{name} {a.prec} opA={a.opA} opB={a.opB} M={M} N={N} K={K}: {ms * 1e3:.1f} us/call, "
+              f"{8.0 * M * N * K / (ms * 1e-3) / 1e12:.2f} TFLOP/s", flush=True)
     f.close()
 
 
@@ -87,7 +108,10 @@ def main(argv=None):
     g.add_argument("--opA", type=int, default=0, choices=[0, 1, 2])
     g.add_argument("--opB", type=int, default=0, choices=[0, 1, 2])
     g.add_argument("--reps", type=int, default=4)
+    g.add_argument("--rounds", type=int, default=1,
+                   help="timed rounds (alternating with --vendor); the fastest round is reported")
     g.add_argument("--seed", type=int, default=0)
+    g.add_argument("--vendor", action="store_true", help="also time torch.addmm (ROCm BLAS)")
     j = sub.add_parser("jacobi")
     j.add_argument("--m", type=int, required=True)
     j.add_argument("--kind", choices=["random", "gram"], default="random")
