@@ -83,7 +83,7 @@ __device__ __forceinline__ v2 ldc_(const v2* p, bool ok) {
 
 template <typename v2>
 struct Args {
-  int M, N, K, tilesM, tilesN, n1, n2, splitk;
+  int M, N, K, tilesM, tilesN, n1, n2, splitk, tri;
   v2 alpha, beta;
   const v2* A[2];
   const v2* B[2];
@@ -117,6 +117,13 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
     K = (K - kb < a.splitk) ? (int)(K - kb) : a.splitk;
     A += (OPA == OP_N) ? kb * lda : kb;
     B += (OPB == OP_N) ? kb : kb * ldb;
+  }
+  if (a.tri != 0) {  // op(A) triangular (square): only the K range of its nonzero part
+    const int kb = (a.tri == 2) ? i0 : 0;
+    const int ke = (a.tri == 1) ? min(K, i0 + BM) : K;
+    A += (OPA == OP_N) ? (long)kb * lda : kb;
+    B += (OPB == OP_N) ? kb : (long)kb * ldb;
+    K = ke - kb;
   }
 
   v2 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
@@ -277,7 +284,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ge
   long start = 0;
   for (int q = 0; q < x; ++q) start += (total - q + 7) / 8;
   const long g = start + (L >> 3);
-  const int tile = (int)(g % per);
+  // lower triangular op(A): the longest K ranges (last tile rows) are handed out first
+  const int tile = (a.tri == 1) ? (int)(per - 1 - g % per) : (int)(g % per);
   long rest = g / per;
   const int b1 = (int)(rest % a.n1);
   rest /= a.n1;
@@ -412,6 +420,13 @@ __device__ __forceinline__ void gemmx_tile(const Args<float2>& a, int prob, int 
     A += (OPA == OP_N) ? kb * lda : kb;
     B += (OPB == OP_N) ? kb : kb * ldb;
   }
+  if (a.tri != 0) {  // op(A) triangular (square): only the K range of its nonzero part
+    const int kb = (a.tri == 2) ? i0 : 0;
+    const int ke = (a.tri == 1) ? min(K, i0 + BM) : K;
+    A += (OPA == OP_N) ? (long)kb * lda : kb;
+    B += (OPB == OP_N) ? kb : (long)kb * ldb;
+    K = ke - kb;
+  }
   constexpr bool AK = (OPA != OP_N), BK_ = (OPB == OP_N);  // k contiguous in storage
   constexpr int TILE = 4 * 64 * 4;                          // uint4 per operand tile
 
@@ -538,7 +553,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ge
   long start = 0;
   for (int q = 0; q < x; ++q) start += (total - q + 7) / 8;
   const long g = start + (L >> 3);
-  const int tile = (int)(g % per);
+  // lower triangular op(A): the longest K ranges (last tile rows) are handed out first
+  const int tile = (a.tri == 1) ? (int)(per - 1 - g % per) : (int)(g % per);
   long rest = g / per;
   const int b1 = (int)(rest % a.n1);
   rest /= a.n1;
@@ -578,6 +594,8 @@ void dispatchx(hipStream_t s, const int* opA, int nprob, int opB, const Args<flo
 
 template <typename v2>
 Args<v2> make_args(int M, int N, int K, v2 alpha, v2 beta, const Batch& bt) {
+  if (bt.tri < 0 || bt.tri > 2 || (bt.tri != 0 && (M != K || bt.splitk != 0)))
+    throw HipError{hipErrorInvalidValue, "gemm: a triangular op(A) must be square, no split-K"};
   Args<v2> a;
   a.M = M;
   a.N = N;
@@ -587,6 +605,7 @@ Args<v2> make_args(int M, int N, int K, v2 alpha, v2 beta, const Batch& bt) {
   a.n1 = bt.n1;
   a.n2 = bt.n2;
   a.splitk = bt.splitk;
+  a.tri = bt.tri;
   a.alpha = alpha;
   a.beta = beta;
   a.sA1 = bt.sA1;

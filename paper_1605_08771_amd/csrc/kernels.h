@@ -8,10 +8,13 @@ namespace feast {
 // Two nested strided batch dimensions (element strides), n1 x n2 problems.
 // With splitk > 0 the first batch dimension instead cuts K into chunks of splitk (the
 // n1 partial products go to C + b1 * sC1; sA1/sB1 are ignored).
+// tri = 1 (2): op(A) is square lower (upper) triangular, M = K; each row tile multiplies only
+// the K range of the nonzero part (the zero part of A is never read).
 struct Batch {
   int n1 = 1, n2 = 1;
   long sA1 = 0, sA2 = 0, sB1 = 0, sB2 = 0, sC1 = 0, sC2 = 0;
   int splitk = 0;
+  int tri = 0;
 };
 
 // Optional per-thread hook that brackets every GEMM launch (kernel-level profiling).

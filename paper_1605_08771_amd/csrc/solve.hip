@@ -244,6 +244,9 @@ void sweeps(hipStream_t s, const typename V2<T>::t* LU, const typename V2<T>::t*
   bi.sB1 = bi.sC1 = sides * per;
   Batch bg = bi;  // factor blocks x right-hand sides, over nodes
   bg.sA1 = (long)np * np;
+  Batch bl = bi, bu = bi;  // the inverse blocks are lower (L, U^H) or upper (U, L^H)
+  bl.tri = 1;
+  bu.tri = 2;
   const long ldn[2] = {np, np}, ldb[2] = {nbt, nbt};
   v2* Bs[2] = {B, B + per};
   v2* Zs[2] = {Z, Z + per};
@@ -254,9 +257,9 @@ void sweeps(hipStream_t s, const typename V2<T>::t* LU, const typename V2<T>::t*
     const v2* rhs[2] = {Bs[0] + r0, Bs[1] + r0};
     v2* out[2] = {Zs[0] + r0, Zs[1] + r0};
     if (sides == 2)
-      gemm_pair_t<T>(s, OP_N, OP_C, nbt, m0, nbt, 1.0, iA, ldb, rhs, ldn, 0.0, out, ldn, bi);
+      gemm_pair_t<T>(s, OP_N, OP_C, nbt, m0, nbt, 1.0, iA, ldb, rhs, ldn, 0.0, out, ldn, bl);
     else
-      gemm_t<T>(s, OP_N, OP_N, nbt, m0, nbt, 1.0, iA[0], nbt, rhs[0], np, 0.0, out[0], np, bi);
+      gemm_t<T>(s, OP_N, OP_N, nbt, m0, nbt, 1.0, iA[0], nbt, rhs[0], np, 0.0, out[0], np, bl);
     const int rest = np - r0 - nbt;
     if (rest > 0) {
       const v2* T2[2] = {LU + (r0 + nbt) + (long)r0 * np, LU + r0 + (long)(r0 + nbt) * np};
@@ -276,9 +279,9 @@ void sweeps(hipStream_t s, const typename V2<T>::t* LU, const typename V2<T>::t*
     const v2* rhs[2] = {Zs[0] + r0, Zs[1] + r0};
     v2* out[2] = {Bs[0] + r0, Bs[1] + r0};
     if (sides == 2)
-      gemm_pair_t<T>(s, OP_N, OP_C, nbt, m0, nbt, 1.0, iA, ldb, rhs, ldn, 0.0, out, ldn, bi);
+      gemm_pair_t<T>(s, OP_N, OP_C, nbt, m0, nbt, 1.0, iA, ldb, rhs, ldn, 0.0, out, ldn, bu);
     else
-      gemm_t<T>(s, OP_N, OP_N, nbt, m0, nbt, 1.0, iA[0], nbt, rhs[0], np, 0.0, out[0], np, bi);
+      gemm_t<T>(s, OP_N, OP_N, nbt, m0, nbt, 1.0, iA[0], nbt, rhs[0], np, 0.0, out[0], np, bu);
     if (r0 > 0) {
       const v2* T2[2] = {LU + (long)r0 * np, LU + r0};
       const v2* yin[2] = {Bs[0] + r0, Bs[1] + r0};
