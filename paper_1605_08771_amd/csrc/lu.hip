@@ -7,7 +7,9 @@
 //          pivoting): each launch reduces the per-workgroup pivot candidates of the previous
 //          launch, reads the pivot row, and eliminates every other active row, then leaves
 //          the candidates of the next column.  The pivot row is read-only in that launch, so
-//          workgroups never race.
+//          workgroups never race.  The column steps update only the columns of their group
+//          of PG; at the end of a group one launch applies the group's rank-PG update to the
+//          panel's later columns and a second one writes the group's rows of U there.
 //   swaps: the panel's pivot rows are moved to the top with the fewest row moves (at most
 //          2 x 64 rows, LAPACK swap order) over all columns, and the permutation is updated;
 //   U12:   unit-lower triangular solve with the 64x64 L11 staged in LDS;
@@ -22,6 +24,10 @@ namespace {
 constexpr int NBP = 64;   // panel width
 constexpr int NSUB = 8;   // panels per outer panel (trailing updates contract over NSUB * NBP)
 constexpr int RPW = 256;  // rows per workgroup in the panel kernels
+#ifndef FEAST_LU_PG
+#define FEAST_LU_PG 16
+#endif
+constexpr int PG = FEAST_LU_PG;  // panel columns per group of column steps
 
 template <typename T>
 struct V2;
@@ -151,9 +157,9 @@ __global__ __launch_bounds__(RPW) void panel_search_kernel(const typename V2<T>:
 
 template <typename T>
 __global__ __launch_bounds__(RPW) void panel_step_kernel(
-    typename V2<T>::t* __restrict__ M, int np, int k, int w, int jj, int nwg, int maxwg,
-    const double* __restrict__ pval_in, const int* __restrict__ prow_in, double* pval_out,
-    int* prow_out, int* retired, int* pivrows, int* flag) {
+    typename V2<T>::t* __restrict__ M, int np, int k, int w, int jj, int gend, int nwg,
+    int maxwg, const double* __restrict__ pval_in, const int* __restrict__ prow_in,
+    double* pval_out, int* prow_out, int* retired, int* pivrows, int* flag) {
   typedef typename V2<T>::t v2;
   __shared__ double sv[RPW];
   __shared__ int sr[RPW];
@@ -183,7 +189,7 @@ __global__ __launch_bounds__(RPW) void panel_step_kernel(
     __syncthreads();
   }
   const int p = s_p;
-  const int width = w - jj;  // columns c .. k+w-1
+  const int width = gend - jj;  // columns c .. k+gend-1 (the rest of this column's group)
   if (t < width) upiv[t] = M[p + (long)(c + t) * np];
   __syncthreads();
   if (t == 0) {
@@ -217,12 +223,121 @@ __global__ __launch_bounds__(RPW) void panel_step_kernel(
       }
     }
   }
-  if (jj + 1 < w) {
+  if (jj + 1 < gend) {  // at a group's last column the group update leaves the candidates
     block_argmax(cand, crow, sv, sr);
     if (t == 0) {
       pval_out[node * maxwg + blockIdx.x] = cand;
       prow_out[node * maxwg + blockIdx.x] = crow;
     }
+  }
+}
+
+// Rows of U of the group's pivots in the panel columns k+gend .. k+w-1 (nu of them) into Us:
+// forward substitution with the unit-lower PG x PG block of the group's multipliers, from
+// the pivot rows as the column steps left them (updated by earlier groups only).
+template <typename T>
+__device__ void group_u_rows(const typename V2<T>::t* __restrict__ M, int np, int k, int g0,
+                             int ng, int gend, int nu, const int* __restrict__ prows,
+                             typename V2<T>::t (*Ls)[PG], typename V2<T>::t (*Us)[NBP]) {
+  typedef typename V2<T>::t v2;
+  const int t = threadIdx.x;
+  for (int e = t; e < ng * ng; e += RPW) {
+    const int j = e % ng, i = e / ng;
+    Ls[j][i] = M[prows[j] + (long)(k + g0 + i) * np];
+  }
+  for (int e = t; e < ng * nu; e += RPW) {
+    const int j = e % ng, q = e / ng;
+    Us[j][q] = M[prows[j] + (long)(k + gend + q) * np];
+  }
+  __syncthreads();
+  if (t < nu) {
+    for (int j = 1; j < ng; ++j) {
+      v2 u = Us[j][t];
+      for (int i = 0; i < j; ++i) {
+        const v2 l = Ls[j][i], v = Us[i][t];
+        u.x -= l.x * v.x - l.y * v.y;
+        u.y -= l.x * v.y + l.y * v.x;
+      }
+      Us[j][t] = u;
+    }
+  }
+  __syncthreads();
+}
+
+// End of a group of column steps (columns k+g0 .. k+gend-1): every active row (not a pivot
+// of this panel) gets M[r, c] -= sum_i L[r, k+g0+i] U[i, c] over the later panel columns
+// c >= k+gend, then the workgroup leaves its pivot candidates for column k+gend.  The pivot
+// rows themselves are left as they are (other workgroups read them here); the next launch
+// writes their U values.
+template <typename T>
+__global__ __launch_bounds__(RPW) void panel_group_kernel(
+    typename V2<T>::t* __restrict__ M, int np, int k, int w, int g0, int gend, int maxwg,
+    double* pval_out, int* prow_out, const int* __restrict__ retired,
+    const int* __restrict__ pivrows) {
+  typedef typename V2<T>::t v2;
+  __shared__ v2 Ls[PG][PG];
+  __shared__ v2 Us[PG][NBP];
+  __shared__ int sp[PG];
+  __shared__ double sv[RPW];
+  __shared__ int sr[RPW];
+  const int node = blockIdx.y;
+  const int t = threadIdx.x;
+  M += (long)node * np * np;
+  retired += node * np;
+  const int ng = gend - g0, nu = w - gend;
+  if (t < ng) sp[t] = pivrows[node * NBP + g0 + t];
+  __syncthreads();
+  group_u_rows<T>(M, np, k, g0, ng, gend, nu, sp, Ls, Us);
+  const int row = k + blockIdx.x * RPW + t;
+  double cand = -1.0;
+  int crow = 0x7fffffff;
+  if (row < np && retired[row] != k + 1) {
+    v2 l[PG];
+#pragma unroll
+    for (int i = 0; i < PG; ++i)
+      l[i] = (i < ng) ? M[row + (long)(k + g0 + i) * np] : v2{0, 0};
+    for (int q = 0; q < nu; ++q) {
+      v2 m = M[row + (long)(k + gend + q) * np];
+#pragma unroll
+      for (int i = 0; i < PG; ++i) {
+        const v2 u = Us[i][q];
+        m.x -= l[i].x * u.x - l[i].y * u.y;
+        m.y -= l[i].x * u.y + l[i].y * u.x;
+      }
+      M[row + (long)(k + gend + q) * np] = m;
+      if (q == 0) {
+        cand = (double)m.x * m.x + (double)m.y * m.y;
+        crow = row;
+      }
+    }
+  }
+  block_argmax(cand, crow, sv, sr);
+  if (t == 0) {
+    pval_out[node * maxwg + blockIdx.x] = cand;
+    prow_out[node * maxwg + blockIdx.x] = crow;
+  }
+}
+
+// One workgroup per node: the group's pivot rows get their rows of U in the later panel
+// columns (the same forward substitution as panel_group_kernel).
+template <typename T>
+__global__ __launch_bounds__(RPW) void panel_group_pivots_kernel(
+    typename V2<T>::t* __restrict__ M, int np, int k, int w, int g0, int gend,
+    const int* __restrict__ pivrows) {
+  typedef typename V2<T>::t v2;
+  __shared__ v2 Ls[PG][PG];
+  __shared__ v2 Us[PG][NBP];
+  __shared__ int sp[PG];
+  const int node = blockIdx.y;
+  const int t = threadIdx.x;
+  M += (long)node * np * np;
+  const int ng = gend - g0, nu = w - gend;
+  if (t < ng) sp[t] = pivrows[node * NBP + g0 + t];
+  __syncthreads();
+  group_u_rows<T>(M, np, k, g0, ng, gend, nu, sp, Ls, Us);
+  for (int e = t; e < ng * nu; e += RPW) {
+    const int j = e % ng, q = e / ng;
+    M[sp[j] + (long)(k + gend + q) * np] = Us[j][q];
   }
 }
 
@@ -412,11 +527,23 @@ void lu_factor(hipStream_t s, typename V2<T>::t* M, int np, int nc, LuWork& w) {
     hipLaunchKernelGGL((panel_search_kernel<T>), dim3(nwg, nc), dim3(RPW), 0, s, M, np, kp, pv[0],
                        pr[0], maxwg);
     FEAST_LAUNCH_CHECK();
-    for (int jj = 0; jj < width; ++jj) {
-      hipLaunchKernelGGL((panel_step_kernel<T>), dim3(nwg, nc), dim3(RPW), 0, s, M, np, kp, width,
-                         jj, nwg, maxwg, pv[jj & 1], pr[jj & 1], pv[(jj + 1) & 1],
-                         pr[(jj + 1) & 1], w.retired, w.pivrows, w.flag);
-      FEAST_LAUNCH_CHECK();
+    for (int g0 = 0; g0 < width; g0 += PG) {
+      const int gend = std::min(width, g0 + PG);
+      for (int jj = g0; jj < gend; ++jj) {
+        hipLaunchKernelGGL((panel_step_kernel<T>), dim3(nwg, nc), dim3(RPW), 0, s, M, np, kp,
+                           width, jj, gend, nwg, maxwg, pv[jj & 1], pr[jj & 1], pv[(jj + 1) & 1],
+                           pr[(jj + 1) & 1], w.retired, w.pivrows, w.flag);
+        FEAST_LAUNCH_CHECK();
+      }
+      if (gend < width) {  // later panel columns: the group's rank-PG update, then its U rows
+        hipLaunchKernelGGL((panel_group_kernel<T>), dim3(nwg, nc), dim3(RPW), 0, s, M, np, kp,
+                           width, g0, gend, maxwg, pv[gend & 1], pr[gend & 1], w.retired,
+                           w.pivrows);
+        FEAST_LAUNCH_CHECK();
+        hipLaunchKernelGGL((panel_group_pivots_kernel<T>), dim3(1, nc), dim3(RPW), 0, s, M, np,
+                           kp, width, g0, gend, w.pivrows);
+        FEAST_LAUNCH_CHECK();
+      }
     }
     hipLaunchKernelGGL(panel_moves_kernel, dim3(nc), dim3(128), 0, s, np, kp, width, w.pivrows,
                        w.moves, w.perm);
