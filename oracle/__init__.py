@@ -15,60 +15,78 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libfeast_oracle.so")
+_SO_FAULTS = os.path.join(_HERE, "libfeast_oracle_faults.so")
 _lib = None
+_ref = None      # the reference library
+_faults = None   # the test build with planted mistakes (mutation tests only)
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
 
 
 def build(force=False):
-    """Compile the oracle with the host C compiler (no GPU code involved)."""
+    """Compile the oracle with the host C compiler (no GPU code involved): the reference
+    library, and a separate test build with the planted mistakes of the mutation tests
+    (-DORACLE_FAULTS); the reference library holds no fault branches."""
     src = os.path.join(_HERE, "feast_oracle.c")
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
-        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-fcx-fortran-rules", "-std=c11",
-               "-D_DEFAULT_SOURCE", "-Wall", src, "-o", _SO + ".tmp", "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(_SO + ".tmp", _SO)
+    hdr = os.path.join(_HERE, "feast_oracle.h")
+    newest = max(os.path.getmtime(src), os.path.getmtime(hdr))
+    for so, extra in ((_SO, []), (_SO_FAULTS, ["-DORACLE_FAULTS"])):
+        if force or not os.path.exists(so) or os.path.getmtime(so) < newest:
+            cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-fcx-fortran-rules",
+                   "-std=c11", "-D_DEFAULT_SOURCE", "-Wall", *extra, src, "-o", so + ".tmp",
+                   "-lm"]
+            subprocess.check_call(cmd)
+            os.replace(so + ".tmp", so)
     return _SO
 
 
 def lib():
-    global _lib
+    """The library the oracle functions call: the reference build, or the fault build while
+    set_fault(code != 0) is in effect."""
+    global _lib, _ref
     if _lib is None:
-        if not os.path.exists(_SO):
-            build()
-        L = ctypes.CDLL(_SO)
-        L.or_gauss_legendre.argtypes = [ctypes.c_int, _dp, _dp]
-        L.or_contour.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp]
-        L.or_zlu.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _ip]
-        L.or_zlu_solve.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _ip, ctypes.c_int, _dp,
-                                   ctypes.c_int, ctypes.c_int]
-        L.or_jacobi_eigh.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int]
-        L.or_filter_apply.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int,
-                                      ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp,
-                                      ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int]
-        L.or_rayleigh_ritz.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp,
-                                       ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                       ctypes.c_double, ctypes.c_double, _dp, _dp, _ip]
-        L.or_feast_solve.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int,
-                                     ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                     ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                                     ctypes.c_double, _dp, ctypes.c_int, _dp, ctypes.c_int,
-                                     _dp, _dp, _ip, _ip, _dp]
-        L.or_feast_solve_ex.argtypes = L.or_feast_solve.argtypes + [ctypes.c_int, _dp]
-        L.or_xrfeast_solve.argtypes = [ctypes.c_int] + L.or_feast_solve.argtypes[:7] + [
-            ctypes.c_int, ctypes.c_int] + L.or_feast_solve.argtypes[8:] + [ctypes.c_int, _dp]
-        L.or_feast_solve_gen.argtypes = L.or_feast_solve.argtypes[:4] + [_dp, ctypes.c_int] + \
-            L.or_feast_solve.argtypes[4:] + [ctypes.c_int, _dp]
-        L.or_filter_apply_gen.argtypes = L.or_filter_apply.argtypes[:4] + [_dp, ctypes.c_int] + \
-            L.or_filter_apply.argtypes[4:]
-        L.or_select_pairs.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double,
-                                      ctypes.c_int, _ip]
-        L.or_num_threads.restype = ctypes.c_int
-        L.or_set_num_threads.argtypes = [ctypes.c_int]
-        L.or_set_fault.argtypes = [ctypes.c_int]
-        _lib = L
+        if _ref is None:
+            _ref = _load(_SO)
+        _lib = _ref
     return _lib
+
+
+def _load(path):
+    if not os.path.exists(path):
+        build()
+    L = ctypes.CDLL(path)
+    L.or_gauss_legendre.argtypes = [ctypes.c_int, _dp, _dp]
+    L.or_contour.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp]
+    L.or_zlu.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _ip]
+    L.or_zlu_solve.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _ip, ctypes.c_int, _dp,
+                               ctypes.c_int, ctypes.c_int]
+    L.or_jacobi_eigh.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int]
+    L.or_filter_apply.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp,
+                                  ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int]
+    L.or_rayleigh_ritz.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp,
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, _dp, _dp, _ip]
+    L.or_feast_solve.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_double, _dp, ctypes.c_int, _dp, ctypes.c_int,
+                                 _dp, _dp, _ip, _ip, _dp]
+    L.or_feast_solve_ex.argtypes = L.or_feast_solve.argtypes + [ctypes.c_int, _dp]
+    L.or_xrfeast_solve.argtypes = [ctypes.c_int] + L.or_feast_solve.argtypes[:7] + [
+        ctypes.c_int, ctypes.c_int] + L.or_feast_solve.argtypes[8:] + [ctypes.c_int, _dp]
+    L.or_feast_solve_gen.argtypes = L.or_feast_solve.argtypes[:4] + [_dp, ctypes.c_int] + \
+        L.or_feast_solve.argtypes[4:] + [ctypes.c_int, _dp]
+    L.or_filter_apply_gen.argtypes = L.or_filter_apply.argtypes[:4] + [_dp, ctypes.c_int] + \
+        L.or_filter_apply.argtypes[4:]
+    L.or_select_pairs.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_int, _ip]
+    L.or_num_threads.restype = ctypes.c_int
+    L.or_set_num_threads.argtypes = [ctypes.c_int]
+    if hasattr(L, "or_set_fault"):
+        L.or_set_fault.argtypes = [ctypes.c_int]
+    return L
 
 
 def _ptr(a):
@@ -85,8 +103,19 @@ def _fort(a, dtype):
 
 
 def set_fault(code: int):
-    """Plant a known mistake in the oracle (0 = none); for the mutation tests of the pins."""
-    lib().or_set_fault(int(code))
+    """Plant a known mistake in the oracle (0 = none); for the mutation tests of the pins.
+    A nonzero code routes every oracle call to the separate fault build until set_fault(0)
+    returns them to the reference library."""
+    global _lib, _faults
+    if code:
+        if _faults is None:
+            _faults = _load(_SO_FAULTS)
+        _faults.or_set_fault(int(code))
+        _lib = _faults
+    else:
+        if _faults is not None:
+            _faults.or_set_fault(0)
+        _lib = None
 
 
 def num_threads() -> int:

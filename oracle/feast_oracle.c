@@ -38,9 +38,15 @@
 
 typedef double complex zc;
 
-/* Planted-mistake switch for the mutation tests of the pins (0 = correct oracle). */
+/* Planted-mistake switch for the mutation tests of the pins.  Only the separate test build
+ * compiled with -DORACLE_FAULTS has it; in the reference build g_fault is the constant 0, so
+ * every planted branch below folds away at compile time and the library holds none of them. */
+#ifdef ORACLE_FAULTS
 static int g_fault = 0;
 void or_set_fault(int code) { g_fault = code; }
+#else
+#define g_fault 0
+#endif
 
 int or_num_threads(void) {
 #ifdef _OPENMP

@@ -59,7 +59,10 @@ int or_select_pairs(int r, const double* lam, const double* res, double emin, do
                     int m0, int* sel);
 int or_num_threads(void);
 void or_set_num_threads(int n);
+/* Test build only (compiled with -DORACLE_FAULTS): plant mistake `code` (0 = none). */
+#ifdef ORACLE_FAULTS
 void or_set_fault(int code);
+#endif
 
 #ifdef __cplusplus
 }
