@@ -111,6 +111,8 @@ typedef struct {
 #define FEAST_B_NOT_SPD 4      /* the filtered block is rank deficient (Q^H Q singular) */
 #define FEAST_NONFINITE 5      /* NaN/Inf in A, X or an intermediate */
 #define FEAST_ZERO_PIVOT 6     /* exact zero pivot in a shifted factorization */
+#define FEAST_EIG_FAILED 7     /* the dense Hermitian eigensolve of a Rayleigh-Ritz step (or of
+                                  the Gram matrix of XFEAST/RFEAST) did not converge */
 #define FEAST_ERR_ALLOC (-100)
 #define FEAST_ERR_HIP (-101)
 #define FEAST_ERR_UNSUPPORTED (-102)
@@ -201,6 +203,26 @@ int feast_filter_apply_gen(feast_handle h, feast_dtype dt, int n, const void* A,
                            feast_precision prec, const void* X, int ldx, int m0, void* Q,
                            int ldq);
 
+/* Outcome of the last feast_solve / feast_solve_gen on a handle (host values). */
+typedef struct {
+  int iters;               /* iterations run */
+  int filter_applications; /* applications of rho(A) (each solves the n_c shifted systems for
+                              m0 right-hand sides, both adjoint sides for complex A) */
+  int counted;             /* Ritz pairs that step 3 counted (the *m of the call) */
+  double max_res;          /* largest residual over the counted pairs at the last iteration */
+  double time_ms;          /* duration of the call on the handle's stream (HIP events) */
+} feast_solve_info;
+
+/* The step-3 decision of the last feast_solve / feast_solve_gen on h (Appendix, FEAST step 3;
+ * RFEAST step 3 for the variant).  info: NULL or filled as above.  counted: NULL or host array
+ * of m0 ints, counted[k] = 1 when Ritz pair k is one the convergence test counts: lambda_k
+ * inside I and, with the filter-value test on, mu_k > 1/2 (or, for RFEAST without it, one of
+ * the m_e lowest residuals inside I); 0 otherwise.  When the last iterate met step 3 as the
+ * paper states it (every pair inside I at or below tol), the filter-value test is not needed
+ * and mu_k (feast_get_filter_values) holds the scalar filter rho(lambda_k) instead of a
+ * measured x_k^H rho(A) x_k.  Returns the number of counted pairs, or -1 (h NULL) / -4. */
+int feast_get_solve_info(feast_handle h, feast_solve_info* info, int* counted, int m0);
+
 /* One problem of a batch (device arrays owned by the caller, host outputs as in feast_solve).
  * X0 may be NULL (seeded Gaussian start); X0 and X share ldx. */
 typedef struct {
@@ -217,13 +239,19 @@ typedef struct {
   int* status;       /* host: the feast_solve return code of this problem */
   double* mu;        /* host, m0, or NULL: filter values mu_k of the returned Ritz vectors
                         (written when opt->spurious = 1 or opt->prec is a mixed mode) */
+  int* counted;      /* host, m0, or NULL: the step-3 mask of feast_get_solve_info */
+  double* trace;     /* host, opt->max_iter, or NULL: the residual trace of feast_solve */
+  feast_solve_info* info; /* host, or NULL: iterations, filter applications, time */
 } feast_problem;
 
 /* Independent FEAST problems (Sec. 1: disjoint intervals, or independent matrices, are solved
  * independently and in parallel).  Problems are ordered by decreasing n^3 (largest first)
  * and handed to nstreams workers, each with its own HIP stream (default priority) and its own
  * workspace, so small problems overlap on the device.  opt supplies n_c, max_iter, tol, prec,
- * refine_max, spurious and seed; m0 and anorm come from each problem.
+ * refine_max, spurious and seed; m0 and anorm come from each problem.  Work already queued on
+ * the handle's stream (for example the writes of A and X0) completes before any worker reads
+ * the inputs: every worker stream waits for an event recorded on it at entry.  The call
+ * returns after every worker has synchronised its stream.
  * Argument positions: h=1 dt=2 nprob=3 probs=4 opt=5 nstreams=6 (1..32).
  * Returns 0 when every problem returned FEAST_OK, else the number of problems that did not
  * (their own codes are in *status). */

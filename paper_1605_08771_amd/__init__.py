@@ -21,7 +21,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "feast.h")
 FEAST_R64, FEAST_C128 = 0, 1
 FEAST_FP64, FEAST_FP32_IR, FEAST_BF16X3_IR = 0, 1, 2
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "M0_TOO_SMALL", 3: "NO_EIGENVALUES",
-          4: "B_NOT_SPD", 5: "NONFINITE", 6: "ZERO_PIVOT", -100: "ERR_ALLOC",
+          4: "B_NOT_SPD", 5: "NONFINITE", 6: "ZERO_PIVOT", 7: "EIG_FAILED", -100: "ERR_ALLOC",
           -101: "ERR_HIP", -102: "ERR_UNSUPPORTED"}
 KCLASS = {"lu": 0, "solve": 1, "rr": 2, "refine": 3, "other": 4, "eig": 5}
 
@@ -37,6 +37,12 @@ class FeastOpts(ctypes.Structure):
                 ("method", ctypes.c_int), ("expand", ctypes.c_int)]
 
 
+class FeastSolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("filter_applications", ctypes.c_int),
+                ("counted", ctypes.c_int), ("max_res", ctypes.c_double),
+                ("time_ms", ctypes.c_double)]
+
+
 class FeastProblem(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("lda", ctypes.c_int), ("ldx", ctypes.c_int),
                 ("m0", ctypes.c_int), ("A", ctypes.c_void_p), ("emin", ctypes.c_double),
@@ -44,7 +50,10 @@ class FeastProblem(ctypes.Structure):
                 ("X", ctypes.c_void_p), ("lambda_", ctypes.POINTER(ctypes.c_double)),
                 ("res", ctypes.POINTER(ctypes.c_double)), ("m", ctypes.POINTER(ctypes.c_int)),
                 ("iters", ctypes.POINTER(ctypes.c_int)), ("status", ctypes.POINTER(ctypes.c_int)),
-                ("mu", ctypes.POINTER(ctypes.c_double))]
+                ("mu", ctypes.POINTER(ctypes.c_double)),
+                ("counted", ctypes.POINTER(ctypes.c_int)),
+                ("trace", ctypes.POINTER(ctypes.c_double)),
+                ("info", ctypes.POINTER(FeastSolveInfo))]
 
 
 _lib = None
@@ -91,6 +100,8 @@ def lib():
             [_vp, ctypes.c_int] + L.feast_filter_apply.argtypes[5:]
         L.feast_get_timings.argtypes = [_vp, _dp, ctypes.c_int]
         L.feast_get_filter_values.argtypes = [_vp, _dp, ctypes.c_int]
+        L.feast_get_solve_info.argtypes = [_vp, ctypes.POINTER(FeastSolveInfo), _ip,
+                                           ctypes.c_int]
         L.feast_solve_batched.argtypes = [_vp, ctypes.c_int, ctypes.c_int,
                                           ctypes.POINTER(FeastProblem), ctypes.POINTER(FeastOpts),
                                           ctypes.c_int]
@@ -115,6 +126,12 @@ def _ld(t, name):
     if t.dim() != 2:
         raise ValueError(f"{name} must be 2-D")
     if t.numel() == 0:
+        return max(1, t.shape[0])
+    if t.shape[1] == 1:  # a one-column tensor's column stride carries no layout (torch sets 1)
+        if t.stride(0) != 1 and t.shape[0] > 1:
+            raise ValueError(f"{name} must be column-major (use fortran(t))")
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must live on the HIP device")
         return max(1, t.shape[0])
     if t.stride(0) != 1 or t.stride(1) < max(1, t.shape[0]):
         raise ValueError(f"{name} must be column-major (use fortran(t))")
@@ -254,11 +271,22 @@ class Feast:
                                trace.ctypes.data_as(_dp))
         out = dict(status=st, X=X, lam=lam, res=res, m=m.value, iters=iters.value,
                    trace=trace[: iters.value])
+        self._outcome(out, m0)
         if spurious or prec != FEAST_FP64:
             mu = np.zeros(m0)
             lib().feast_get_filter_values(self.h, mu.ctypes.data_as(_dp), m0)
             out["mu"] = mu
         return out
+
+    def _outcome(self, out, m0):
+        """The library's step-3 decision and counts for the last solve on this handle."""
+        import numpy as np
+        info = FeastSolveInfo()
+        counted = np.zeros(m0, dtype=np.int32)
+        lib().feast_get_solve_info(self.h, ctypes.byref(info), counted.ctypes.data_as(_ip), m0)
+        out["counted"] = np.flatnonzero(counted)
+        out["filter_applications"] = info.filter_applications
+        out["time_ms"] = info.time_ms
 
     def filter_apply_gen(self, A, B, X, emin, emax, n_c, Q=None):
         """Q = rho(B^{-1} A) X for the Hermitian-definite pencil (A, B) (FP64)."""
@@ -308,6 +336,7 @@ class Feast:
                                    trace.ctypes.data_as(_dp))
         out = dict(status=st, X=X, lam=lam, res=res, m=m.value, iters=iters.value,
                    trace=trace[: iters.value])
+        self._outcome(out, m0)
         if spurious:
             mu = np.zeros(m0)
             lib().feast_get_filter_values(self.h, mu.ctypes.data_as(_dp), m0)
@@ -334,6 +363,8 @@ class Feast:
             m0 = pr["m0"]
             X = fortran(torch.empty((n, m0), dtype=A.dtype, device=A.device))
             lam, res, mu = np.zeros(m0), np.zeros(m0), np.zeros(m0)
+            counted, trace = np.zeros(m0, dtype=np.int32), np.zeros(max_iter)
+            info = FeastSolveInfo()
             m, it, st = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(-999)
             X0 = pr.get("X0")
             if X0 is not None:
@@ -347,16 +378,20 @@ class Feast:
                                   X=X.data_ptr(), lambda_=lam.ctypes.data_as(_dp),
                                   res=res.ctypes.data_as(_dp), m=ctypes.pointer(m),
                                   iters=ctypes.pointer(it), status=ctypes.pointer(st),
-                                  mu=mu.ctypes.data_as(_dp))
-            keep += [X, lam, res, m, it, st, mu]
-            outs.append((X, lam, res, m, it, st, mu))
+                                  mu=mu.ctypes.data_as(_dp),
+                                  counted=counted.ctypes.data_as(_ip),
+                                  trace=trace.ctypes.data_as(_dp), info=ctypes.pointer(info))
+            keep += [X, lam, res, m, it, st, mu, counted, trace, info]
+            outs.append((X, lam, res, m, it, st, mu, counted, trace, info))
         opts = FeastOpts(n_c=n_c, m0=1, max_iter=max_iter, refine_max=refine_max, tol=tol,
                          anorm=0.0, prec=prec, seed=0, spurious=int(spurious))
         torch.cuda.synchronize()
         bad = lib().feast_solve_batched(self.h, dt, len(problems), arr, ctypes.byref(opts),
                                         nstreams)
         results = [dict(status=st.value, X=X, lam=lam, res=res, m=m.value, iters=it.value,
-                        mu=mu) for (X, lam, res, m, it, st, mu) in outs]
+                        mu=mu, counted=np.flatnonzero(counted), trace=trace[: it.value],
+                        filter_applications=info.filter_applications, time_ms=info.time_ms)
+                   for (X, lam, res, m, it, st, mu, counted, trace, info) in outs]
         return bad, results
 
     def solve_slices(self, A, edges, m0, anorm=0.0, X0=None, n_c=8, tol=1e-12, max_iter=200,
@@ -364,9 +399,10 @@ class Feast:
         """Eigenpairs of one matrix A in the open slices (edges[k], edges[k+1]), solved as
         independent intervals (Sec. 1) on concurrent streams.  m0: one size for all slices or
         one per slice; X0: None (seeded starts) or one start block per slice.  Returns
-        (count_not_ok, per-slice results, eigenvalues of all slices in ascending order).  A
-        pair counts for its slice when its Ritz value lies inside it (and mu_k > 1/2 when the
-        filter-value test is on)."""
+        (count_not_ok, per-slice results, eigenvalues of all slices in ascending order).  The
+        pairs of a slice are those the library's step 3 counted for it ("counted"); each
+        slice's result also carries its residual trace, iteration count, filter applications
+        and solve time, so the imbalance between slices of uneven spectral density shows."""
         import numpy as np
         edges = [float(e) for e in edges]
         if len(edges) < 2 or any(b <= a for a, b in zip(edges, edges[1:])):
@@ -384,13 +420,7 @@ class Feast:
         bad, outs = self.solve_batched(probs, n_c=n_c, tol=tol, max_iter=max_iter, prec=prec,
                                        refine_max=refine_max, spurious=spurious,
                                        nstreams=nstreams)
-        found = []
-        for i, o in enumerate(outs):
-            ok = (o["lam"] > edges[i]) & (o["lam"] < edges[i + 1])
-            if spurious or prec != FEAST_FP64:
-                ok &= o["mu"] > 0.5
-            o["counted"] = np.flatnonzero(ok)
-            found.append(o["lam"][ok])
+        found = [o["lam"][o["counted"]] for o in outs]
         return bad, outs, np.sort(np.concatenate(found)) if found else np.zeros(0)
 
     # ---------------------------------------------------------------- building blocks

@@ -18,6 +18,28 @@ using namespace feast;
 
 namespace {
 
+void gauss_legendre_gw(int n, std::vector<double>& x, std::vector<double>& w);
+
+}  // namespace
+
+// Nodes and weights of the quadrature (readings of Sec. 1, eq. contour_int_quad): circle of
+// centre c = (emin + emax)/2 and radius r = (emax - emin)/2, Gauss-Legendre abscissae x_j on
+// the upper half circle theta_j = (pi/2)(1 - x_j), z_j = c + r e^{i theta_j},
+// omega_j = (w_j / 4) r e^{i theta_j}.
+void feast::quadrature_nodes(double emin, double emax, int nc, zd* z, zd* omega) {
+  std::vector<double> x, w;
+  gauss_legendre_gw(nc, x, w);
+  const double c = 0.5 * (emin + emax), r = 0.5 * (emax - emin);
+  for (int j = 0; j < nc; ++j) {
+    double th = 0.5 * M_PI * (1.0 - x[j]);
+    double ct = std::cos(th), st = std::sin(th);
+    z[j] = zmake(c + r * ct, r * st);
+    omega[j] = zmake(0.25 * w[j] * r * ct, 0.25 * w[j] * r * st);
+  }
+}
+
+namespace {
+
 // ---------------------------------------------------------------------------------------
 // Gauss-Legendre nodes/weights (the "Gauss quadrature" of Sec. 1) by the Golub-Welsch
 // characterisation: the nodes are the eigenvalues of the symmetric tridiagonal Jacobi matrix
@@ -116,6 +138,11 @@ struct EventPool {
   }
 };
 
+// Sweep cap of the dense Hermitian eigensolves: the block-pair Jacobi takes about 10 sweeps
+// on random Hermitian matrices and 30-33 on the strongly graded Gram matrices of the
+// expanded-subspace methods; a solve that needs more than this reports FEAST_EIG_FAILED.
+constexpr int kJacobiMaxSweeps = 60;
+
 constexpr int NCLASS = 6;
 enum { K_LU = 0, K_SOLVE = 1, K_RR = 2, K_REFINE = 3, K_OTHER = 4, K_EIG = 5 };
 
@@ -149,8 +176,8 @@ struct KernelProfiler : GemmProfiler {
     pending.push_back({a, b, K_EIG, 1.0});
     eig_pending.push_back({(long long)std::max(sweeps, 0), 1});
   }
-  void flush() {  // stream must be synchronised
-    for (auto& e : eig_pending) launches[K_EIG] += e.first - 1;
+  void flush() {  // stream must be synchronised; an eigensolve counts its sweeps (>= 0)
+    for (auto& e : eig_pending) launches[K_EIG] += e.first - 1;  // the record below adds 1
     eig_pending.clear();
     for (auto& r : pending) {
       float t = 0;
@@ -164,7 +191,11 @@ struct KernelProfiler : GemmProfiler {
   }
 };
 
-// Phase timer: pairs of events accumulated into phase totals at flush().
+enum { P_FACTOR = 0, P_SOLVE = 1, P_ACC = 2, P_RR = 3, P_REFINE = 4, P_TOTAL = 5 };
+
+// Phase timer: pairs of events accumulated into phase totals at flush().  The whole call is
+// bracketed by two events of its own (begin_total / end_total), which the pool's reuse after
+// each flush never hands out again.
 struct PhaseTimer {
   EventPool pool;
   struct Rec {
@@ -173,12 +204,27 @@ struct PhaseTimer {
   };
   std::vector<Rec> pending;
   double ms[6] = {0};
+  hipEvent_t t_begin = nullptr, t_end = nullptr;
+  bool total_open = false;
   hipEvent_t mark(hipStream_t s) {
     hipEvent_t e = pool.take();
     FEAST_HIP(hipEventRecord(e, s));
     return e;
   }
   void add(hipEvent_t a, hipEvent_t b, int phase) { pending.push_back({a, b, phase}); }
+  void begin_total(hipStream_t s) {
+    if (!t_begin) FEAST_HIP(hipEventCreate(&t_begin));
+    if (!t_end) FEAST_HIP(hipEventCreate(&t_end));
+    FEAST_HIP(hipEventRecord(t_begin, s));
+    total_open = true;
+  }
+  // Records the end of the call; the caller synchronises the stream, then flushes.
+  void end_total(hipStream_t s) {
+    if (!total_open) return;
+    FEAST_HIP(hipEventRecord(t_end, s));
+    pending.push_back({t_begin, t_end, P_TOTAL});
+    total_open = false;
+  }
   void flush() {
     for (auto& r : pending) {
       float t = 0;
@@ -190,9 +236,13 @@ struct PhaseTimer {
   }
   void clear() {
     for (double& v : ms) v = 0;
+    total_open = false;
+  }
+  ~PhaseTimer() {
+    if (t_begin) (void)hipEventDestroy(t_begin);
+    if (t_end) (void)hipEventDestroy(t_end);
   }
 };
-enum { P_FACTOR = 0, P_SOLVE = 1, P_ACC = 2, P_RR = 3, P_REFINE = 4, P_TOTAL = 5 };
 
 struct ScopedProf {
   KernelProfiler* kp;
@@ -238,6 +288,10 @@ struct feast_ctx {
   Buf b_Q1, b_Q2, b_AQ, b_AX, b_G, b_part, b_Rinv, b_rrtmp, b_H, b_jac, b_V, b_d, b_lam, b_res,
       b_rank, b_W, b_flag, b_diag, b_pow, b_mu, b_Reig, b_Y64, b_AY, b_rho, b_rmax, b_kpart;
   std::vector<double> mu;
+  // outcome of the last solve: step 3's counted pairs, filter applications, iterations
+  std::vector<int> counted;
+  int last_filters = 0, last_iters = 0, last_count = 0;
+  double last_max_res = 0;
   PhaseTimer timer;
   KernelProfiler prof;
   std::map<int, JacobiGraph> jgraphs;  // recorded Jacobi sweeps, by padded order
@@ -268,17 +322,9 @@ int ensure_factors(feast_ctx* h, int dt, int n, const void* A, int lda, double e
   const int nbt = sweep_block(n);
   const int np = (n + nbt - 1) / nbt * nbt;
   // nodes and weights
-  std::vector<double> x, w;
-  gauss_legendre_gw(nc, x, w);
-  const double c = 0.5 * (emin + emax), r = 0.5 * (emax - emin);
   h->z.resize(nc);
   h->omega.resize(nc);
-  for (int j = 0; j < nc; ++j) {
-    double th = 0.5 * M_PI * (1.0 - x[j]);
-    double ct = std::cos(th), st = std::sin(th);
-    h->z[j] = zmake(c + r * ct, r * st);
-    h->omega[j] = zmake(0.25 * w[j] * r * ct, 0.25 * w[j] * r * st);
-  }
+  quadrature_nodes(emin, emax, nc, h->z.data(), h->omega.data());
   zd* zdev = h->b_z.get<zd>(nc);
   zd* odev = h->b_omega.get<zd>(nc);
   FEAST_HIP(hipMemcpyAsync(zdev, h->z.data(), sizeof(zd) * nc, hipMemcpyHostToDevice, s));
@@ -288,10 +334,19 @@ int ensure_factors(feast_ctx* h, int dt, int n, const void* A, int lda, double e
   lu_work_carve(h->luw, luw, np, nc);
   hipEvent_t e0 = h->timer.mark(s);
   int st = 0;
+  // The shift flags non-finite shifted entries (NaN/Inf in A or B; for FP32 factors also
+  // entries beyond the FP32 range) before any factorization work.
+  auto shifted_finite = [&]() {
+    int flag = 0;
+    FEAST_HIP(hipMemcpyAsync(&flag, h->luw.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEAST_HIP(hipStreamSynchronize(s));
+    return flag == 0;
+  };
+  fill_zero(s, h->luw.flag, sizeof(int));
   if (prec == FEAST_FP64) {
     zd* F = h->b_fac.get<zd>((size_t)nc * np * np);
-    shift_matrices(s, A, lda, dt == FEAST_R64, n, np, zdev, nc, F, B, ldb);
-    if (nonfinite_check(s, F, np, np, np, h->luw.flag)) return FEAST_NONFINITE;
+    shift_matrices(s, A, lda, dt == FEAST_R64, n, np, zdev, nc, F, h->luw.flag, B, ldb);
+    if (!shifted_finite()) return FEAST_NONFINITE;
     {
       ScopedProf sp(h->prof, K_LU);
       lu_factor_f64(s, F, np, nc, h->luw);
@@ -311,7 +366,8 @@ int ensure_factors(feast_ctx* h, int dt, int n, const void* A, int lda, double e
     // FEAST_BF16X3_IR: the FP32 factorization's matrix-core products run as bf16x3.
     SplitBf16Scope split(prec == FEAST_BF16X3_IR);
     zf* F = h->b_fac.get<zf>((size_t)nc * np * np);
-    shift_matrices_f32(s, A, lda, dt == FEAST_R64, n, np, zdev, nc, F, B, ldb);
+    shift_matrices_f32(s, A, lda, dt == FEAST_R64, n, np, zdev, nc, F, h->luw.flag, B, ldb);
+    if (!shifted_finite()) return FEAST_NONFINITE;
     {
       ScopedProf sp(h->prof, K_LU);
       lu_factor_f32(s, F, np, nc, h->luw);
@@ -405,6 +461,7 @@ int filter_core(feast_ctx* h, int dt, int n, int m0, const zd* X, long ldx, zd* 
                 const zd* A = nullptr, long lda = 0, const RitzInfo* ritz = nullptr,
                 int refine = 0, bool adaptive = false) {
   hipStream_t s = h->stream;
+  h->last_filters++;
   const int np = h->f_np, nc = h->f_nc, nbt = h->f_nbt;
   const int sides = (dt == FEAST_C128) ? 2 : 1;
   const size_t blk = (size_t)nc * sides * np * m0;
@@ -549,7 +606,7 @@ int cholqr_pass(feast_ctx* h, int n, int m0, const zd* Q1, zd* Q2, double shift_
     for (double v : hd) tr += v;
     add_diag(s, G, m0, m0, shift_rel * tr);
   }
-  FEAST_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+  fill_zero(s, flag, sizeof(int));
   cholesky_upper(s, G, m0, m0, flag, nullptr);
   int hflag = 0;
   FEAST_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -557,7 +614,7 @@ int cholqr_pass(feast_ctx* h, int n, int m0, const zd* Q1, zd* Q2, double shift_
   if (hflag) return 1;
   zd* Rinv = h->b_Rinv.get<zd>((size_t)m0 * m0);
   zd* tmp = h->b_rrtmp.get<zd>((size_t)m0 * 64);
-  FEAST_HIP(hipMemsetAsync(Rinv, 0, sizeof(zd) * (size_t)m0 * m0, s));
+  fill_zero(s, Rinv, sizeof(zd) * (size_t)m0 * m0);
   upper_inverse(s, G, m0, m0, Rinv, m0, tmp);
   zgemm(s, OP_N, OP_N, n, m0, m0, zmake(1, 0), Q1, n, Rinv, m0, zmake(0, 0), Q2, n);
   return 0;
@@ -628,9 +685,9 @@ int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m
   int* dflag = h->b_flag.get<int>(64);
   hipEvent_t ej = h->prof.on ? h->prof.pool.take() : nullptr;
   if (ej) FEAST_HIP(hipEventRecord(ej, s));
-  int sweeps = jacobi_eigh(s, H, m0, d, V, jw, dflag, 40, &h->jgraphs[mp], mp);
+  int sweeps = jacobi_eigh(s, H, m0, d, V, jw, dflag, kJacobiMaxSweeps, &h->jgraphs[mp], mp);
   if (ej) h->prof.eig(s, ej, sweeps);
-  (void)sweeps;
+  if (sweeps < 0) return FEAST_EIG_FAILED;
   double* lam = h->b_lam.get<double>(mp);
   zd* W = h->b_W.get<zd>((size_t)m0 * m0);
   int* rank = h->b_rank.get<int>(mp);
@@ -710,7 +767,8 @@ int solve_setup(feast_ctx* h, feast_dtype dt, int n, const void* A, int lda, dou
 // (Method 1), after scaling B's columns to unit length in place (a diagonal scaling keeps the
 // span; it keeps RFEAST's short residual columns above the rank threshold):
 // B^H B = V S^2 V^H (Jacobi), U = B V S^{-1} over the directions with s^2 > 1e-14 s^2_max.
-// Returns r (0: no direction left) or -1 if the Gram matrix is not finite.
+// Returns r (0: no direction left), -1 if the Gram matrix is not finite or -2 if its
+// eigensolve did not converge.
 int gram_orthonormal(feast_ctx* h, int n, int k, zd* B, zd* U) {
   hipStream_t s = h->stream;
   normalize_columns(s, B, n, n, k);
@@ -731,8 +789,9 @@ int gram_orthonormal(feast_ctx* h, int n, int k, zd* B, zd* U) {
   int* dflag = h->b_flag.get<int>(64);
   hipEvent_t ej = h->prof.on ? h->prof.pool.take() : nullptr;
   if (ej) FEAST_HIP(hipEventRecord(ej, s));
-  int sweeps = jacobi_eigh(s, G, k, d, V, jw, dflag, 40, &h->jgraphs[mp], mp);
+  int sweeps = jacobi_eigh(s, G, k, d, V, jw, dflag, kJacobiMaxSweeps, &h->jgraphs[mp], mp);
   if (ej) h->prof.eig(s, ej, sweeps);
+  if (sweeps < 0) return -2;
   std::vector<double> hd(k);
   FEAST_HIP(hipMemcpyAsync(hd.data(), d, sizeof(double) * k, hipMemcpyDeviceToHost, s));
   FEAST_HIP(hipStreamSynchronize(s));
@@ -753,6 +812,40 @@ int gram_orthonormal(feast_ctx* h, int n, int k, zd* B, zd* U) {
   zgemm(s, OP_N, OP_N, n, r, k, zmake(1, 0), B, n, T, k, zmake(0, 0), U, n);
   FEAST_HIP(hipStreamSynchronize(s));  // keep_h is reused by the next call
   return r;
+}
+
+// mu_k (host, k < cnt) for Ritz pairs whose filter value was not measured because the last
+// iterate met step 3 as the paper states it: the scalar filter rho(lambda_k) of the
+// quadrature, which x_k^H rho(A) x_k equals up to the square of the (converged) residual.
+void scalar_filter_mu(feast_ctx* h, const double* lam_dev, int cnt) {
+  hipStream_t s = h->stream;
+  double* rho = h->b_rho.get<double>(std::max(cnt, 1));
+  filter_values(s, lam_dev, (const zd*)h->b_z.p, (const zd*)h->b_omega.p, h->f_nc, cnt, rho);
+  h->mu.assign(cnt, 0.0);
+  FEAST_HIP(hipMemcpyAsync(h->mu.data(), rho, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
+  FEAST_HIP(hipStreamSynchronize(s));
+}
+
+// Step 3 as the paper states it: every Ritz pair inside I counts, and the iteration stops
+// when their largest residual is at most tol (and fewer than m0 lie inside I after the first
+// iteration).  Pairs inside I with a residual at most tol are eigenpairs inside I (their
+// eigenvalue lies within res * anorm of lambda_k), so when this test passes the filter-value
+// test cannot remove any of them and is not needed.
+bool plain_step3_converged(const double* lam, const double* res, int cnt, double emin,
+                           double emax, double tol, int m0, int it) {
+  int in = 0;
+  double r = 0;
+  for (int k = 0; k < cnt; ++k)
+    if (lam[k] > emin && lam[k] < emax) {
+      in++;
+      r = std::max(r, res[k]);
+    }
+  return in > 0 && r <= tol && !(in >= m0 && it >= 2);
+}
+
+// Status of a gram_orthonormal result r (0 when r is a usable basis width).
+int gram_status(int r) {
+  return r == -2 ? FEAST_EIG_FAILED : r < 0 ? FEAST_NONFINITE : r == 0 ? FEAST_B_NOT_SPD : 0;
 }
 
 // Selection of Sec. 2 (Method 1; Method 2 uses the same): every pair inside I, then the pairs
@@ -783,7 +876,7 @@ int select_pairs(int r, const double* lam, const double* res, double emin, doubl
 // Xs holds X_0 on entry (n x m0, complex).  Outputs as feast_solve.
 int xr_solve(feast_ctx* h, feast_dtype dt, int n, const zd* Ac, long ldac, double anorm,
              double emin, double emax, const feast_opts* opt, zd* Xs, void* X, int ldx,
-             double* lambda, double* res, int* m, int* iters, double* trace, hipEvent_t t0) {
+             double* lambda, double* res, int* m, int* iters, double* trace) {
   hipStream_t s = h->stream;
   const int m0 = opt->m0, sx = opt->expand, variant = opt->method;
   const int K = sx * m0;
@@ -828,7 +921,7 @@ int xr_solve(feast_ctx* h, feast_dtype dt, int n, const zd* Ac, long ldac, doubl
     int take = 0, me = -1, rs = 0, mcount = 0;
     if (variant == FEAST_METHOD_XFEAST) {
       int r = gram_orthonormal(h, n, kcols, W, U);  // step 1
-      rs = r < 0 ? FEAST_NONFINITE : r == 0 ? FEAST_B_NOT_SPD : 0;
+      rs = gram_status(r);
       if (!rs)
         rs = rr_core(h, Ac, ldac, n, U, n, r, emin, emax, anorm, lam_h.data(), res_h.data(),
                      &mcount, mixed ? Reig : nullptr, true);  // step 2.i
@@ -837,7 +930,7 @@ int xr_solve(feast_ctx* h, feast_dtype dt, int n, const zd* Ac, long ldac, doubl
       kcols = m0;
       for (int j = 1; j <= sx && !rs; ++j) {  // step 2
         int r = gram_orthonormal(h, n, kcols, W, U);
-        rs = r < 0 ? FEAST_NONFINITE : r == 0 ? FEAST_B_NOT_SPD : 0;
+        rs = gram_status(r);
         if (!rs)
           rs = rr_core(h, Ac, ldac, n, U, n, r, emin, emax, anorm, lam_h.data(), res_h.data(),
                        &mcount, Reig, true);
@@ -864,10 +957,10 @@ int xr_solve(feast_ctx* h, feast_dtype dt, int n, const zd* Ac, long ldac, doubl
       res[a] = a < take ? res_h[sel[a]] : INFINITY;
     }
     const bool seeded = mixed && take == m0;
-    if (seeded) {
-      gather_columns(s, Reig, n, dsel, n, take, Rsel, n);
-      gather_values(s, (const double*)h->b_lam.p, dsel, take, lsel);
-    }
+    const bool plain = spur && plain_step3_converged(lambda, res, take, emin, emax, opt->tol,
+                                                     m0, it);
+    if (seeded || plain) gather_values(s, (const double*)h->b_lam.p, dsel, take, lsel);
+    if (seeded) gather_columns(s, Reig, n, dsel, n, take, Rsel, n);
     RitzInfo ri{Rsel, lsel};
     // rho(A) X_{i+1}: XFEAST's newest block (in place of the oldest), RFEAST's next X'
     zd* dst = variant == FEAST_METHOD_XFEAST ? W + (size_t)slot * n * m0 : W;
@@ -875,7 +968,10 @@ int xr_solve(feast_ctx* h, feast_dtype dt, int n, const zd* Ac, long ldac, doubl
       return filter_core(h, dt, n, m0, Xs, n, dst, n, Ac, ldac, seeded ? &ri : nullptr,
                          opt->refine_max);
     };
-    if (spur) {
+    if (plain) {
+      scalar_filter_mu(h, lsel, take);
+      h->mu.resize(m0, 0.0);
+    } else if (spur) {
       fs = filter_next();
       if (fs) {
         st = fs;
@@ -891,7 +987,7 @@ int xr_solve(feast_ctx* h, feast_dtype dt, int n, const zd* Ac, long ldac, doubl
     std::vector<int> cand;
     for (int a = 0; a < take; ++a) {
       if (!(lambda[a] > emin && lambda[a] < emax)) continue;
-      if (spur && !(h->mu[a] > 0.5)) continue;
+      if (spur && !plain && !(h->mu[a] > 0.5)) continue;
       cand.push_back(a);
     }
     if (variant == FEAST_METHOD_RFEAST && !spur && me >= 0 && (int)cand.size() > me) {
@@ -901,6 +997,9 @@ int xr_solve(feast_ctx* h, feast_dtype dt, int n, const zd* Ac, long ldac, doubl
     double r = 0;
     for (int a : cand) r = std::max(r, res[a]);
     mm = (int)cand.size();
+    h->counted.assign(m0, 0);
+    for (int a : cand) h->counted[a] = 1;
+    h->last_max_res = r;
     if (trace) trace[it - 1] = r;
     if (mm == 0) {
       if (prev_m == 0) {
@@ -927,10 +1026,11 @@ int xr_solve(feast_ctx* h, feast_dtype dt, int n, const zd* Ac, long ldac, doubl
   if (it > opt->max_iter) it = opt->max_iter;
   *iters = it;
   *m = mm;
+  h->last_iters = it;
+  h->last_count = mm;
   if (dt == FEAST_R64) complex_to_real(s, Xs, n, (double*)X, ldx, n, m0);
   else copy_matrix(s, Xs, n, (zd*)X, ldx, n, m0);
-  hipEvent_t t1 = h->timer.mark(s);
-  h->timer.add(t0, t1, P_TOTAL);
+  h->timer.end_total(s);
   FEAST_HIP(hipStreamSynchronize(s));
   finish_timing(h);
   return st;
@@ -990,6 +1090,7 @@ const char* feast_status_string(int st) {
     case FEAST_B_NOT_SPD: return "filtered block is rank deficient (B' not positive definite)";
     case FEAST_NONFINITE: return "non-finite value in the input or an intermediate";
     case FEAST_ZERO_PIVOT: return "exact zero pivot in a shifted factorization";
+    case FEAST_EIG_FAILED: return "the dense reduced eigensolver did not converge";
     case FEAST_ERR_ALLOC: return "device allocation failed";
     case FEAST_ERR_HIP: return "HIP runtime error";
     case FEAST_ERR_UNSUPPORTED: return "unsupported option";
@@ -1026,7 +1127,7 @@ int feast_filter_apply(feast_handle h, feast_dtype dt, int n, const void* A, int
   try {
     hipStream_t s = h->stream;
     h->timer.clear();
-    hipEvent_t t0 = h->timer.mark(s);
+    h->timer.begin_total(s);
     int st = ensure_factors(h, dt, n, A, lda, emin, emax, n_c, prec);
     if (st) {
       finish_timing(h);
@@ -1057,8 +1158,7 @@ int feast_filter_apply(feast_handle h, feast_dtype dt, int n, const void* A, int
     st = filter_core(h, dt, n, m0, Xc, ldxc, Qc, ldqc, Ac, ldac, nullptr,
                      prec == FEAST_BF16X3_IR ? 30 : 10, true);
     if (st == 0 && dt == FEAST_R64) complex_to_real(s, Qc, n, (double*)Q, ldq, n, m0);
-    hipEvent_t t1 = h->timer.mark(s);
-    h->timer.add(t0, t1, P_TOTAL);
+    h->timer.end_total(s);
     FEAST_HIP(hipStreamSynchronize(s));
     finish_timing(h);
     return st;
@@ -1089,7 +1189,7 @@ int feast_rayleigh_ritz(feast_handle h, feast_dtype dt, int n, const void* A, in
   try {
     hipStream_t s = h->stream;
     h->timer.clear();
-    hipEvent_t t0 = h->timer.mark(s);
+    h->timer.begin_total(s);
     long ldac;
     const zd* Ac = complex_A(h, dt, n, A, lda, &ldac);
     zd* Qc;
@@ -1104,8 +1204,7 @@ int feast_rayleigh_ritz(feast_handle h, feast_dtype dt, int n, const void* A, in
     }
     int st = rr_core(h, Ac, ldac, n, Qc, ldqc, m0, emin, emax, anorm, lambda, res, m);
     if (st == 0 && dt == FEAST_R64) complex_to_real(s, Qc, n, (double*)Q, ldq, n, m0);
-    hipEvent_t t1 = h->timer.mark(s);
-    h->timer.add(t0, t1, P_TOTAL);
+    h->timer.end_total(s);
     FEAST_HIP(hipStreamSynchronize(s));
     finish_timing(h);
     return st;
@@ -1127,10 +1226,13 @@ int solve_impl(feast_handle h, feast_dtype dt, int n, const void* A, int lda, co
                int ldb, double emin, double emax, const feast_opts* opt, const void* X0, void* X,
                int ldx, double* lambda, double* res, int* m, int* iters, double* trace) {
   const int m0 = opt->m0;
+  h->counted.assign(m0, 0);
+  h->last_filters = h->last_iters = h->last_count = 0;
+  h->last_max_res = 0;
   try {
     hipStream_t s = h->stream;
     h->timer.clear();
-    hipEvent_t t0 = h->timer.mark(s);
+    h->timer.begin_total(s);
     long ldac = 0;
     const zd* Ac = nullptr;
     double anorm = 0;
@@ -1146,7 +1248,7 @@ int solve_impl(feast_handle h, feast_dtype dt, int n, const void* A, int lda, co
     }
     if (opt->method != FEAST_METHOD_FEAST)
       return xr_solve(h, dt, n, Ac, ldac, anorm, emin, emax, opt, Xw, X, ldx, lambda, res, m,
-                      iters, trace, t0);
+                      iters, trace);
     zd* Qf = h->b_Qc.get<zd>((size_t)n * m0);
     PencilB pb;
     if (B) pb.B = complex_B(h, dt, n, B, ldb, &pb.ld);
@@ -1183,7 +1285,11 @@ int solve_impl(feast_handle h, feast_dtype dt, int n, const void* A, int lda, co
         st = rs;
         break;
       }
-      if (spur) {  // the next step 1 gives mu_k = Re(x_k^H rho(A) x_k)
+      const bool plain = spur && plain_step3_converged(lambda, res, m0, emin, emax, opt->tol,
+                                                       m0, it);
+      if (plain) {
+        scalar_filter_mu(h, (const double*)h->b_lam.p, m0);
+      } else if (spur) {  // the next step 1 gives mu_k = Re(x_k^H rho(A) x_k)
         const zd* bx = rhs(Xw);
         fs = filter_core(h, dt, n, m0, bx, n, Qf, n, Ac, ldac, mixed ? &ri : nullptr);
         if (fs) {
@@ -1198,13 +1304,16 @@ int solve_impl(feast_handle h, feast_dtype dt, int n, const void* A, int lda, co
       finish_timing(h);
       double r = 0;  // step 3
       int cnt = 0;
+      h->counted.assign(m0, 0);
       for (int k = 0; k < m0; ++k) {
         if (!(lambda[k] > emin && lambda[k] < emax)) continue;
-        if (spur && !(h->mu[k] > 0.5)) continue;
+        if (spur && !plain && !(h->mu[k] > 0.5)) continue;
+        h->counted[k] = 1;
         cnt++;
         r = std::max(r, res[k]);
       }
       mm = cnt;
+      h->last_max_res = r;
       if (trace) trace[it - 1] = r;
       if (mm == 0) {
         if (prev_m == 0) {
@@ -1231,10 +1340,11 @@ int solve_impl(feast_handle h, feast_dtype dt, int n, const void* A, int lda, co
     if (it > opt->max_iter) it = opt->max_iter;
     *iters = it;
     *m = mm;
+    h->last_iters = it;
+    h->last_count = mm;
     if (dt == FEAST_R64) complex_to_real(s, Xw, n, (double*)X, ldx, n, m0);
     else copy_matrix(s, Xw, n, (zd*)X, ldx, n, m0);
-    hipEvent_t t1 = h->timer.mark(s);
-    h->timer.add(t0, t1, P_TOTAL);
+    h->timer.end_total(s);
     FEAST_HIP(hipStreamSynchronize(s));
     finish_timing(h);
     return st;
@@ -1328,7 +1438,7 @@ int feast_filter_apply_gen(feast_handle h, feast_dtype dt, int n, const void* A,
   try {
     hipStream_t s = h->stream;
     h->timer.clear();
-    hipEvent_t t0 = h->timer.mark(s);
+    h->timer.begin_total(s);
     int st = ensure_factors(h, dt, n, A, lda, emin, emax, n_c, prec, B, ldb);
     if (st) {
       finish_timing(h);
@@ -1350,8 +1460,7 @@ int feast_filter_apply_gen(feast_handle h, feast_dtype dt, int n, const void* A,
     long ldqc = (dt == FEAST_R64) ? n : ldq;
     st = filter_core(h, dt, n, m0, BX, n, Qc, ldqc);
     if (st == 0 && dt == FEAST_R64) complex_to_real(s, Qc, n, (double*)Q, ldq, n, m0);
-    hipEvent_t t1 = h->timer.mark(s);
-    h->timer.add(t0, t1, P_TOTAL);
+    h->timer.end_total(s);
     FEAST_HIP(hipStreamSynchronize(s));
     finish_timing(h);
     return st;
@@ -1386,6 +1495,17 @@ int feast_solve_batched(feast_handle h, feast_dtype dt, int nprob, const feast_p
       h->workers.push_back(w);
       h->worker_streams.push_back(st);
     }
+    // Inputs written on the caller's stream before this call come first: every worker stream
+    // waits for an event recorded on it before its first launch.
+    hipEvent_t ready = nullptr;
+    FEAST_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    struct EvGuard {
+      hipEvent_t e;
+      ~EvGuard() { (void)hipEventDestroy(e); }
+    } ready_guard{ready};
+    FEAST_HIP(hipEventRecord(ready, h->stream));
+    for (int wi = 0; wi < nstreams; ++wi)
+      FEAST_HIP(hipStreamWaitEvent(h->worker_streams[wi], ready, 0));
     std::vector<int> order(nprob);
     for (int i = 0; i < nprob; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -1405,9 +1525,10 @@ int feast_solve_batched(feast_handle h, feast_dtype dt, int nprob, const feast_p
         int st = -7;
         if (p.lambda && p.res && p.m && p.iters)
           st = feast_solve(wh, dt, p.n, p.A, p.lda, p.emin, p.emax, &o, p.X0, p.X, p.ldx,
-                           p.lambda, p.res, p.m, p.iters, nullptr);
+                           p.lambda, p.res, p.m, p.iters, p.trace);
         if (p.mu)
           for (int q = 0; q < p.m0; ++q) p.mu[q] = q < (int)wh->mu.size() ? wh->mu[q] : 0.0;
+        if (p.info || p.counted) feast_get_solve_info(wh, p.info, p.counted, p.m0);
         if (p.status) *p.status = st;
       }
     };
@@ -1421,6 +1542,21 @@ int feast_solve_batched(feast_handle h, feast_dtype dt, int nprob, const feast_p
   } catch (const HipError& e) {
     return fail_hip(h, e);
   }
+}
+
+int feast_get_solve_info(feast_handle h, feast_solve_info* info, int* counted, int m0) {
+  if (!h) return -1;
+  if (counted && m0 < 0) return -4;
+  if (info) {
+    info->iters = h->last_iters;
+    info->filter_applications = h->last_filters;
+    info->counted = h->last_count;
+    info->max_res = h->last_max_res;
+    info->time_ms = h->timer.ms[P_TOTAL];
+  }
+  if (counted)
+    for (int k = 0; k < m0; ++k) counted[k] = k < (int)h->counted.size() ? h->counted[k] : 0;
+  return h->last_count;
 }
 
 int feast_get_filter_values(feast_handle h, double* mu, int m0) {

@@ -40,6 +40,15 @@ namespace {
 
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256, PAD = 1;
 
+// FEAST_GEMM_3M = 1: FP32 complex products as three real matrix-core products (Gauss's
+// method: 3 MFMAs per 16x16x4 complex step instead of 4, a quarter less matrix-core work; the
+// imaginary part is formed as a difference, with a normwise error bound a small multiple of
+// the four-product one).  0: the four-product form.  FP64 tiles keep the four-product form:
+// the third accumulator set does not fit their registers at two waves per SIMD.
+#ifndef FEAST_GEMM_3M
+#define FEAST_GEMM_3M 1
+#endif
+
 template <typename T>
 struct CT;
 template <>
@@ -171,31 +180,60 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
     FEAST_STORE_AB(0, A0, B0) FEAST_STORE_AB(1, A1, B1)                              \
     FEAST_STORE_AB(2, A2, B2) FEAST_STORE_AB(3, A3, B3)                              \
   }
-#define FEAST_COMPUTE(BUF, CHK)                                                      \
-  {                                                                                  \
-    const int buf = (BUF);                                                           \
-    _Pragma("unroll") for (int kk = 0; kk < BK / 4; ++kk) {                          \
-      const int kidx = kk * 4 + (lane >> 4);                                         \
-      v2 fa[2], fb[2];                                                               \
-      _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                               \
-        fa[mb] = As[buf][kidx][wm * 32 + mb * 16 + (lane & 15)];                      \
-      _Pragma("unroll") for (int nb = 0; nb < 2; ++nb)                               \
-        fb[nb] = Bs[buf][kidx][wn * 32 + nb * 16 + (lane & 15)];                      \
-      _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                               \
-        _Pragma("unroll") for (int nb = 0; nb < 2; ++nb) {                           \
-          if ((CHK) && !live[mb][nb]) continue;                                      \
-          accr[mb][nb] = mfma(fb[nb].x, fa[mb].x, accr[mb][nb]);                     \
-          acci[mb][nb] = mfma(fb[nb].x, fa[mb].y, acci[mb][nb]);                     \
-        }                                                                            \
-      _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                               \
-        _Pragma("unroll") for (int nb = 0; nb < 2; ++nb) {                           \
-          if ((CHK) && !live[mb][nb]) continue;                                      \
-          accr[mb][nb] = mfma(-fb[nb].y, fa[mb].y, accr[mb][nb]);                    \
-          acci[mb][nb] = mfma(fb[nb].y, fa[mb].x, acci[mb][nb]);                     \
-        }                                                                            \
-    }                                                                                \
+  // G3 (FP32): three real products per complex one (Gauss): p1 = re re, p2 = im im,
+  // p3 = (re + im)(re + im); the epilogue forms re = p1 - p2, im = p3 - p1 - p2.
+#define FEAST_COMPUTE(BUF, CHK)                                                       \
+  if constexpr (G3) {                                                                 \
+      const int buf = (BUF);                                                          \
+      _Pragma("unroll") for (int kk = 0; kk < BK / 4; ++kk) {                         \
+        const int kidx = kk * 4 + (lane >> 4);                                        \
+        v2 fa[2], fb[2];                                                              \
+        T sa[2], sb[2];                                                               \
+        _Pragma("unroll") for (int mb = 0; mb < 2; ++mb) {                            \
+          fa[mb] = As[buf][kidx][wm * 32 + mb * 16 + (lane & 15)];                    \
+          sa[mb] = fa[mb].x + fa[mb].y;                                               \
+        }                                                                             \
+        _Pragma("unroll") for (int nb = 0; nb < 2; ++nb) {                            \
+          fb[nb] = Bs[buf][kidx][wn * 32 + nb * 16 + (lane & 15)];                    \
+          sb[nb] = fb[nb].x + fb[nb].y;                                               \
+        }                                                                             \
+        _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                              \
+          _Pragma("unroll") for (int nb = 0; nb < 2; ++nb) {                          \
+            if ((CHK) && !live[mb][nb]) continue;                                     \
+            accr[mb][nb] = mfma(fb[nb].x, fa[mb].x, accr[mb][nb]);                    \
+            acci[mb][nb] = mfma(fb[nb].y, fa[mb].y, acci[mb][nb]);                    \
+          }                                                                           \
+        _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                              \
+          _Pragma("unroll") for (int nb = 0; nb < 2; ++nb) {                          \
+            if ((CHK) && !live[mb][nb]) continue;                                     \
+            accs[mb][nb] = mfma(sb[nb], sa[mb], accs[mb][nb]);                        \
+          }                                                                           \
+      }                                                                               \
+  } else {                                                                            \
+      const int buf = (BUF);                                                          \
+      _Pragma("unroll") for (int kk = 0; kk < BK / 4; ++kk) {                         \
+        const int kidx = kk * 4 + (lane >> 4);                                        \
+        v2 fa[2], fb[2];                                                              \
+        _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                              \
+          fa[mb] = As[buf][kidx][wm * 32 + mb * 16 + (lane & 15)];                    \
+        _Pragma("unroll") for (int nb = 0; nb < 2; ++nb)                              \
+          fb[nb] = Bs[buf][kidx][wn * 32 + nb * 16 + (lane & 15)];                    \
+        _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                              \
+          _Pragma("unroll") for (int nb = 0; nb < 2; ++nb) {                          \
+            if ((CHK) && !live[mb][nb]) continue;                                     \
+            accr[mb][nb] = mfma(fb[nb].x, fa[mb].x, accr[mb][nb]);                    \
+            acci[mb][nb] = mfma(fb[nb].x, fa[mb].y, acci[mb][nb]);                    \
+          }                                                                           \
+        _Pragma("unroll") for (int mb = 0; mb < 2; ++mb)                              \
+          _Pragma("unroll") for (int nb = 0; nb < 2; ++nb) {                          \
+            if ((CHK) && !live[mb][nb]) continue;                                     \
+            accr[mb][nb] = mfma(-fb[nb].y, fa[mb].y, accr[mb][nb]);                   \
+            acci[mb][nb] = mfma(fb[nb].y, fa[mb].x, acci[mb][nb]);                    \
+          }                                                                           \
+      }                                                                               \
   }
-  accv accr[2][2], acci[2][2];
+  constexpr bool G3 = FEAST_GEMM_3M && sizeof(T) == 4;
+  accv accr[2][2], acci[2][2], accs[2][2];
   // A 16 x 16 output block that lies entirely past M or N has nothing to compute; the test
   // is uniform over the wave, so skipping its MFMAs frees the matrix core for other waves.
   bool live[2][2];
@@ -205,6 +243,7 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
     for (int q = 0; q < 2; ++q) {
       accr[p][q] = accv{T(0), T(0), T(0), T(0)};
       acci[p][q] = accv{T(0), T(0), T(0), T(0)};
+      accs[p][q] = accv{T(0), T(0), T(0), T(0)};
       live[p][q] = (i0 + wm * 32 + p * 16 < M) && (j0 + wn * 32 + q * 16 < N);
     }
 
@@ -258,6 +297,11 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
         int j = j0 + wn * 32 + nb * 16 + mfma_row<T>(lane, v);
         if (i < M && j < N) {
           T re = accr[mb][nb][v], im = acci[mb][nb][v];
+          if constexpr (G3) {
+            const T p1 = re, p2 = im;
+            re = p1 - p2;
+            im = accs[mb][nb][v] - p1 - p2;
+          }
           v2 out;
           out.x = alpha.x * re - alpha.y * im;
           out.y = alpha.x * im + alpha.y * re;

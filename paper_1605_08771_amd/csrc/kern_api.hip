@@ -70,11 +70,11 @@ extern "C" int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, co
     LuWork w;
     lu_work_carve(w, wbuf, np, nc);
     if (prec == 0) {
-      shift_matrices(s, A, lda, 0, n, np, zdev, nc, (zd*)LU);
+      shift_matrices(s, A, lda, 0, n, np, zdev, nc, (zd*)LU, w.flag);
       lu_factor_f64(s, (zd*)LU, np, nc, w);
     } else {
       SplitBf16Scope split(prec == 2);
-      shift_matrices_f32(s, A, lda, 0, n, np, zdev, nc, (zf*)LU);
+      shift_matrices_f32(s, A, lda, 0, n, np, zdev, nc, (zf*)LU, w.flag);
       lu_factor_f32(s, (zf*)LU, np, nc, w);
     }
     int flag = 0;

@@ -57,14 +57,20 @@ void cgemm_pair(hipStream_t s, int opA0, int opA1, int opB, int M, int N, int K,
                 const zf* const A[2], const long lda[2], const zf* const B[2], const long ldb[2],
                 zf beta, zf* const C[2], const long ldc[2], const Batch& bt = Batch());
 
+// Quadrature of the filter (feast_api.hip): z[j], omega[j] for j < nc on the host.
+void quadrature_nodes(double emin, double emax, int nc, zd* z, zd* omega);
+
 // ---- LU (lu.hip) ---------------------------------------------------------------------
 // Shifted copies M_j = z_j B - A (j < nc; B = I when B == nullptr) of real (is_real) or
 // complex n x n matrices into np x np factor storage (ld = np, batch stride np*np);
-// rows/cols n..np-1 set to identity.
+// rows/cols n..np-1 set to identity.  *flag (device int, cleared by the caller) becomes
+// nonzero when a shifted entry is not finite in the storage precision.
 void shift_matrices(hipStream_t s, const void* A, long lda, int is_real, int n, int np,
-                    const zd* z_dev, int nc, zd* M, const void* B = nullptr, long ldb = 0);
+                    const zd* z_dev, int nc, zd* M, int* flag, const void* B = nullptr,
+                    long ldb = 0);
 void shift_matrices_f32(hipStream_t s, const void* A, long lda, int is_real, int n, int np,
-                        const zd* z_dev, int nc, zf* M, const void* B = nullptr, long ldb = 0);
+                        const zd* z_dev, int nc, zf* M, int* flag, const void* B = nullptr,
+                        long ldb = 0);
 
 // Workspace for the batched LU with partial pivoting.
 struct LuWork {
@@ -72,7 +78,8 @@ struct LuWork {
   double* pval = nullptr;   // 2 * nc * maxwg, pivot-search partials (value)
   int* prow = nullptr;      // 2 * nc * maxwg, pivot-search partials (row)
   int* pivrows = nullptr;   // nc * 64, pivot rows of the current panel
-  int* moves = nullptr;     // nc * 2 * 128, (dst, src) row moves of the current panel
+  int* moves = nullptr;     // nc * (4 * 64 + 1): per node a count, then up to 2 * 64
+                            // (dst, src) row moves of the current panel
   int* perm = nullptr;      // nc * np, P as a row gather: (P X)[r] = X[perm[r]]
   int* pinv = nullptr;      // nc * np, inverse of perm
   int* flag = nullptr;      // 1 int: set to 1 + column of the first exact zero pivot

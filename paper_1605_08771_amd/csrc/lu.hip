@@ -62,11 +62,12 @@ __device__ inline v2 crecip(v2 a) {  // 1 / a with Smith scaling
   return r;
 }
 
-// M_j = z_j B - A (B == nullptr: B = I); A and B real (is_real) or complex.
+// M_j = z_j B - A (B == nullptr: B = I); A and B real (is_real) or complex.  *flag is set
+// when a shifted entry is not finite in T (NaN/Inf in A or B, or beyond the FP32 range).
 template <typename T>
 __global__ void shift_kernel(const void* __restrict__ A, long lda, const void* __restrict__ B,
                              long ldb, int is_real, int n, int np, const zd* __restrict__ z,
-                             int nc, typename V2<T>::t* __restrict__ M) {
+                             int nc, typename V2<T>::t* __restrict__ M, int* flag) {
   typedef typename V2<T>::t v2;
   long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   long total = (long)np * np;
@@ -95,6 +96,7 @@ __global__ void shift_kernel(const void* __restrict__ A, long lda, const void* _
       double re = z[j].x * br - z[j].y * bi - ar, im = z[j].x * bi + z[j].y * br - ai;
       out.x = (T)re;
       out.y = (T)im;
+      if (!isfinite(out.x) || !isfinite(out.y)) atomicOr(flag, 1);
     } else {
       out.x = (T)(i == c ? 1.0 : 0.0);
       out.y = (T)0;
@@ -511,8 +513,8 @@ void gemm_update<float>(hipStream_t s, zf* M, int np, int nc, int r0, int rows, 
 template <typename T>
 void lu_factor(hipStream_t s, typename V2<T>::t* M, int np, int nc, LuWork& w) {
   const int maxwg = (np + RPW - 1) / RPW;
-  FEAST_HIP(hipMemsetAsync(w.retired, 0, sizeof(int) * (size_t)nc * np, s));
-  FEAST_HIP(hipMemsetAsync(w.flag, 0, sizeof(int), s));
+  fill_zero(s, w.retired, sizeof(int) * (size_t)nc * np);
+  fill_zero(s, w.flag, sizeof(int));
   {
     long tot = (long)np * nc;
     hipLaunchKernelGGL(perm_init_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, w.perm, np, nc);
@@ -628,17 +630,17 @@ void lu_work_carve(LuWork& w, void* base, int np, int nc) {
 }
 
 void shift_matrices(hipStream_t s, const void* A, long lda, int is_real, int n, int np,
-                    const zd* z_dev, int nc, zd* M, const void* B, long ldb) {
+                    const zd* z_dev, int nc, zd* M, int* flag, const void* B, long ldb) {
   long tot = (long)np * np;
   hipLaunchKernelGGL((shift_kernel<double>), dim3((tot + 255) / 256), dim3(256), 0, s, A, lda, B,
-                     ldb, is_real, n, np, z_dev, nc, M);
+                     ldb, is_real, n, np, z_dev, nc, M, flag);
   FEAST_LAUNCH_CHECK();
 }
 void shift_matrices_f32(hipStream_t s, const void* A, long lda, int is_real, int n, int np,
-                        const zd* z_dev, int nc, zf* M, const void* B, long ldb) {
+                        const zd* z_dev, int nc, zf* M, int* flag, const void* B, long ldb) {
   long tot = (long)np * np;
   hipLaunchKernelGGL((shift_kernel<float>), dim3((tot + 255) / 256), dim3(256), 0, s, A, lda, B,
-                     ldb, is_real, n, np, z_dev, nc, M);
+                     ldb, is_real, n, np, z_dev, nc, M, flag);
   FEAST_LAUNCH_CHECK();
 }
 

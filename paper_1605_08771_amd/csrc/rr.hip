@@ -2,6 +2,8 @@
 //   Cholesky-QR orthonormalisation of the filtered block (G = Q^H Q = R^H R, Q <- Q R^{-1}),
 //   block-pair parallel-order two-sided Jacobi for the m0 x m0 reduced matrix, eigenpair sort,
 //   and the residual norms ||A x_k - lambda_k x_k||.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -548,6 +550,23 @@ __global__ void vec_scale_kernel(const zd* w, int n, const double* nrm, zd* v) {
 
 inline dim3 grid1(long n) { return dim3((unsigned)((n + 255) / 256)); }
 
+// Zero fill of `words` 32-bit words then `tail` bytes (grid-stride, 16-byte stores when the
+// buffer allows them).  A kernel rather than hipMemsetAsync, so that clearing flags and
+// scratch stays an ordinary kernel node if a caller records the work into a HIP graph.
+__global__ void zero_fill_kernel(void* p, size_t bytes) {
+  const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  char* c = (char*)p;
+  size_t head = 0;
+  if (((uintptr_t)c & 15) == 0) {
+    const size_t n16 = bytes / 16;
+    uint4* q = (uint4*)c;
+    for (size_t i = tid; i < n16; i += stride) q[i] = make_uint4(0, 0, 0, 0);
+    head = n16 * 16;
+  }
+  for (size_t i = head + tid; i < bytes; i += stride) c[i] = 0;
+}
+
 }  // namespace
 
 void reduce_partials_hermitian(hipStream_t s, const zd* part, int nparts, int m, zd* G, int ldg) {
@@ -712,7 +731,13 @@ void complex_to_real(hipStream_t s, const zd* src, long lds, double* dst, long l
                      rows, cols);
   FEAST_LAUNCH_CHECK();
 }
-void fill_zero(hipStream_t s, void* p, size_t bytes) { FEAST_HIP(hipMemsetAsync(p, 0, bytes, s)); }
+void fill_zero(hipStream_t s, void* p, size_t bytes) {
+  if (bytes == 0) return;
+  const size_t n16 = bytes / 16 + 1;
+  const unsigned blocks = (unsigned)std::min<size_t>((n16 + 255) / 256, 8192);
+  hipLaunchKernelGGL(zero_fill_kernel, dim3(blocks), dim3(256), 0, s, p, bytes);
+  FEAST_LAUNCH_CHECK();
+}
 
 void diag_real(hipStream_t s, const zd* G, int m, int ldg, double* diag) {
   hipLaunchKernelGGL(diag_real_kernel, grid1(m), dim3(256), 0, s, G, m, ldg, diag);
@@ -748,7 +773,7 @@ double norm2_estimate(hipStream_t s, const zd* A, long lda, int n, int iters, zd
 }
 
 int nonfinite_check(hipStream_t s, const zd* a, long ld, int rows, int cols, int* dflag) {
-  FEAST_HIP(hipMemsetAsync(dflag, 0, sizeof(int), s));
+  fill_zero(s, dflag, sizeof(int));
   hipLaunchKernelGGL(nonfinite_kernel, grid1((long)rows * cols), dim3(256), 0, s, a, ld, rows, cols,
                      dflag);
   FEAST_LAUNCH_CHECK();

@@ -166,8 +166,8 @@ void tri_inverse(hipStream_t s, const typename V2<T>::t* LU, int np, int nc, int
                  typename V2<T>::t* invL, typename V2<T>::t* invU, typename V2<T>::t* tmp) {
   typedef typename V2<T>::t v2;
   const size_t invbytes = sizeof(v2) * (size_t)nc * np * nbt;
-  FEAST_HIP(hipMemsetAsync(invL, 0, invbytes, s));
-  FEAST_HIP(hipMemsetAsync(invU, 0, invbytes, s));
+  fill_zero(s, invL, invbytes);
+  fill_zero(s, invU, invbytes);
   hipLaunchKernelGGL((tri_inv64_kernel<T>), dim3(np / TB, nc, 2), dim3(256), 0, s, LU, np, nbt,
                      invL, invU);
   FEAST_LAUNCH_CHECK();

@@ -8,7 +8,10 @@ Spectra follow the paper's hard case (Sec. 1 and Sec. 3 test matrices): eigenval
 densely just outside the search interval, here within 1e-3 of each endpoint.
 
 Random numbers come from numpy's PCG64 seeded with SeedSequence([1605, 8771, tag]); the draw
-order is spectrum, then the Gaussian for U, then X0.
+order is spectrum, then the Gaussian for U, then X0.  For the largest matrices built on the
+device (n >= DEVICE_GAUSSIAN_N) the Gaussian for U is drawn by torch's device generator
+(Philox), seeded by one 63-bit integer drawn from the same PCG64 stream at that point of the
+order: drawing 2 n^2 normals on the host would dominate the set-up time.
 """
 from __future__ import annotations
 
@@ -18,6 +21,7 @@ import math
 import numpy as np
 
 DELTA = 5e-5          # eigenvalues are kept at least this far from either endpoint
+DEVICE_GAUSSIAN_N = 32768  # from this order on, the Gaussian for U is drawn on the device
 EDGE_WIDTH = 1e-3     # width of the edge clusters just inside / just outside the interval
 
 
@@ -100,6 +104,17 @@ def uniform_spectrum(rng, n, emin, emax, delta=DELTA, lo=-1.0, hi=1.0):
 
 def haar_basis(rng, n, complex_, device=None):
     """Q factor of the QR factorization of a seeded i.i.d. Gaussian n x n matrix."""
+    if device is not None and n >= DEVICE_GAUSSIAN_N:
+        import torch
+        gen = torch.Generator(device=device)
+        gen.manual_seed(int(rng.integers(0, 2 ** 63 - 1)))
+        dt = torch.complex128 if complex_ else torch.float64
+        gt = torch.randn((n, n), dtype=dt, device=device, generator=gen)
+        if complex_:
+            gt *= 2 ** 0.5  # torch's complex normal has unit variance: re, im each N(0, 1/2)
+        q, _ = torch.linalg.qr(gt)
+        del gt
+        return q
     g = rng.standard_normal((n, n))
     if complex_:
         g = g + 1j * rng.standard_normal((n, n))
@@ -261,11 +276,11 @@ def config3(n=16384, device=None, seed_tag=3):
     return p
 
 
-def config5(n=32768, device=None, seed_tag=5):
+def config5(n=32768, device=None, seed_tag=5, basis="haar"):
     """n = 32768, 512 eigenvalues in I = (-0.05, 0.05) with 64 within 1e-3 inside each edge,
     no outer cluster, bulk uniform outside; m0 = 768, n_c = 8."""
     p = config2(n=n, device=device, seed_tag=seed_tag, n_in=512, n_in_edge=64, n_out_edge=0,
-                m0=768, n_c=8)
+                m0=768, n_c=8, basis=basis)
     p.name = "C5"
     return p
 

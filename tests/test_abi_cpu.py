@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     L = fm.lib()
-    for code in (0, 1, 2, 3, 4, 5, 6, -100, -101, -102, -3):
+    for code in (0, 1, 2, 3, 4, 5, 6, 7, -100, -101, -102, -3):
         assert len(L.feast_status_string(code)) > 0
 
 
@@ -176,6 +176,15 @@ def test_batched_argument_checks():
     assert f(BAD, 1, 1, arr, ctypes.byref(o), 0) == -6
     assert f(BAD, 1, 1, arr, ctypes.byref(o), 33) == -6
     assert f(BAD, 1, 0, arr, ctypes.byref(o), 4) == 0
+
+
+def test_solve_info_argument_checks():
+    L = fm.lib()
+    info = fm.FeastSolveInfo()
+    assert L.feast_get_solve_info(None, ctypes.byref(info), None, 0) == -1
+    # the binding's structures have the C layout of include/feast.h (LP64: 136 and 32 bytes)
+    assert ctypes.sizeof(fm.FeastProblem) == 136
+    assert ctypes.sizeof(fm.FeastSolveInfo) == 32
 
 
 def test_binding_refuses_mismatched_tensors():

@@ -68,10 +68,14 @@ def test_c2_filter_sampled_columns_vs_exact(fe, c2, prec):
 
 
 def _check_converged(p, out, tol, target=None):
+    """The library's step-3 pairs (its "counted" mask) against the construction."""
     lam, res, mu = out["lam"], out["res"], out.get("mu")
-    sel = (lam > p.emin) & (lam < p.emax)
+    sel = np.zeros(len(lam), dtype=bool)
+    sel[out["counted"]] = True
+    insel = (lam > p.emin) & (lam < p.emax)
+    assert not (sel & ~insel).any()          # counted pairs lie inside I
     if mu is not None:
-        sel &= mu > 0.5
+        assert (mu[sel] > 0.5).all()         # and pass the filter-value test
     inside = (p.lam > p.emin) & (p.lam < p.emax)
     exact = np.sort(p.lam[inside])
     assert out["status"] == 0, out["status"]

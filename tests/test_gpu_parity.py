@@ -160,6 +160,15 @@ def test_solve_complex_hard_case_vs_oracle(fe, orc):
     torch.cuda.synchronize()
     _check_solve(p, out, ref, "c128")
     assert abs(out["iters"] - ref["iters"]) <= 2
+    # phase times: the whole call, measured on its own events, covers the phases
+    t = fe.timings()
+    parts = t["factor_ms"] + t["solve_ms"] + t["accumulate_ms"] + t["rr_ms"] + t["refine_ms"]
+    assert t["total_ms"] > 0 and t["total_ms"] >= 0.99 * parts
+    assert abs(out["time_ms"] - t["total_ms"]) <= 1e-9 * t["total_ms"]
+    # the step-3 mask: every pair inside I (plain FEAST), as many as m
+    ins = np.flatnonzero((out["lam"] > p.emin) & (out["lam"] < p.emax))
+    np.testing.assert_array_equal(out["counted"], ins)
+    assert out["filter_applications"] == out["iters"]
 
 
 def test_solve_status_codes(fe):
@@ -179,6 +188,17 @@ def test_solve_status_codes(fe):
     An = np.array(p.A)
     An[7, 3] = np.nan
     assert fe.solve(_dev(An), -0.2, 0.2, 40, max_iter=10, anorm=p.anorm, X0=X0)["status"] == 5
+    # FP32 factors: a NaN, and an entry beyond the FP32 range, are reported the same way
+    for prec in (1, 2):
+        fe.invalidate()
+        assert fe.solve(_dev(An), -0.2, 0.2, 40, max_iter=10, anorm=p.anorm, X0=X0,
+                        prec=prec, refine_max=0)["status"] == 5
+    Ab = np.array(p.A)
+    Ab[11, 11] = 1e39
+    fe.invalidate()
+    assert fe.solve(_dev(Ab), -0.2, 0.2, 40, max_iter=10, anorm=p.anorm, X0=X0, prec=1,
+                    refine_max=0)["status"] == 5
+    fe.invalidate()
     # X0 == NULL: seeded Gaussian start on the device, anorm estimated by power iteration
     out = fe.solve(A, -0.2, 0.2, 40, max_iter=20, seed=7)
     torch.cuda.synchronize()
@@ -345,6 +365,10 @@ def test_slices_of_one_matrix_vs_oracle(fe, orc):
     assert bad == 0, [o["status"] for o in outs]
     exact = np.sort(lam[(lam > -0.3) & (lam < 0.3)])
     np.testing.assert_allclose(found, exact, rtol=0, atol=1e-10 * p.anorm)
+    for o in outs:  # the per-slice report
+        assert len(o["trace"]) == o["iters"] and o["trace"][-1] <= 1e-12
+        assert o["time_ms"] > 0 and o["filter_applications"] >= o["iters"]
+        assert len(o["counted"]) == o["m"]
     for k, o in enumerate(outs):
         a, b = edges[k], edges[k + 1]
         ref = orc.feast_solve("c128", p.A, a, b, 8, m0s[k], 1e-12, 200, p.anorm, X0s[k],
