@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/feast.h"
+#include "../../include/feast_noalloc.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -1094,6 +1095,9 @@ const char* feast_status_string(int st) {
     case FEAST_ERR_ALLOC: return "device allocation failed";
     case FEAST_ERR_HIP: return "HIP runtime error";
     case FEAST_ERR_UNSUPPORTED: return "unsupported option";
+    case FEAST_ERR_SCRATCH:
+      return "the problem needs more than the static scratch array of the allocation-free "
+             "entry point";
     default: return st < 0 ? "invalid argument" : "unknown status";
   }
 }

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     L = fm.lib()
-    for code in (0, 1, 2, 3, 4, 5, 6, 7, -100, -101, -102, -3):
+    for code in (0, 1, 2, 3, 4, 5, 6, 7, -100, -101, -102, -103, -3):
         assert len(L.feast_status_string(code)) > 0
 
 
@@ -176,6 +176,38 @@ def test_batched_argument_checks():
     assert f(BAD, 1, 1, arr, ctypes.byref(o), 0) == -6
     assert f(BAD, 1, 1, arr, ctypes.byref(o), 33) == -6
     assert f(BAD, 1, 0, arr, ctypes.byref(o), 4) == 0
+
+
+def test_noalloc_argument_checks():
+    """The allocation-free filter entry point validates its arguments and its scratch limit on
+    the host, before any device work."""
+    L = fm.lib()
+    f = L.feast_filter_apply_noalloc
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                  ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    ok = dict(dt=1, n=100, A=DEV, lda=100, emin=-0.1, emax=0.1, n_c=8, X=DEV, ldx=100, m0=10,
+              Q=BAD, ldq=100)
+
+    def call(**kw):
+        a = {**ok, **kw}
+        return f(a["dt"], a["n"], a["A"], a["lda"], a["emin"], a["emax"], a["n_c"], a["X"],
+                 a["ldx"], a["m0"], a["Q"], a["ldq"], None)
+    assert call(dt=3) == -1
+    assert call(n=0) == -2
+    assert call(A=None) == -3
+    assert call(lda=99) == -4
+    assert call(emin=float("nan")) == -5
+    assert call(emax=-0.2) == -6
+    assert call(n_c=0) == -7
+    assert call(X=None) == -8
+    assert call(ldx=50) == -9
+    assert call(m0=101) == -10
+    assert call(Q=DEV) == -11
+    assert call(ldq=1) == -12
+    # 8 complex factors of order 4096 alone exceed the 256 MiB array
+    assert call(n=4096, lda=4096, ldx=4096, ldq=4096) == -103
+    assert b"scratch" in L.feast_status_string(-103)
 
 
 def test_solve_info_argument_checks():
