@@ -13,7 +13,10 @@ extern "C" {
 /* C = alpha op(A) op(B) + beta C on the matrix cores; op: 0 = N, 1 = T, 2 = C (conjugate
  * transpose).  prec 0: complex128 data and FP64 MFMA; prec 1: complex64 data and FP32 MFMA;
  * prec 2: complex64 data, each operand split into bf16 hi + lo parts, three bf16 MFMA products
- * (hi hi + hi lo + lo hi) with FP32 accumulation (relative error ~2^-16 per product term).
+ * (hi hi + hi lo + lo hi) with FP32 accumulation (relative error ~2^-16 per product term);
+ * prec 3: complex128 data, each complex product from three real FP64 MFMA products
+ * (Re Re, Im Im, (Re + Im)(Re + Im)), the form the Rayleigh-Ritz products use.
+ * Complex64 products (prec 1) always use the three-product form.
  * alpha, beta: host arrays {re, im}.  A and B may be NULL when K == 0 (C = beta C).  This is the dense contraction used by the LU trailing
  * updates, the block triangular sweeps and Q^H A Q (Sec. 1 linear solves; Appendix step 2).
  * Argument positions: prec=1 opA=2 opB=3 M=4 N=5 K=6 alpha=7 A=8 lda=9 B=10 ldb=11 beta=12
@@ -26,8 +29,9 @@ int feast_kern_gemm(int prec, int opA, int opB, int M, int N, int K, const doubl
  * factorizations behind each quadrature term of Sec. 1 eq. (contour_int_quad).
  * z: host array of 2*nc doubles (interleaved nodes).  np = n rounded up as the library pads
  * (returned in *np_out when LU is NULL, without other work).  LU: nc blocks of np x np
- * (ld np, complex128 for prec 0, complex64 for prec 1 and 2; prec 2 runs the trailing updates
- * as bf16x3 products, see feast_kern_gemm) receiving unit-lower L and U; perm:
+ * (ld np, complex128 for prec 0, complex64 for prec 1 and 2; the trailing updates are
+ * four-product FP64 (prec 0) or three-product FP32 (prec 1) products, or bf16x3 products
+ * (prec 2), see feast_kern_gemm) receiving unit-lower L and U; perm:
  * nc blocks of np ints with (P M)[r] = M[perm[r]].  Synchronises the stream; returns 6 on an
  * exact zero pivot. */
 int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, const double* z, void* LU,

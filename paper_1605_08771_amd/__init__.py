@@ -425,15 +425,19 @@ class Feast:
 
     # ---------------------------------------------------------------- building blocks
     def gemm(self, opA, opB, A, B, C, alpha=1.0, beta=0.0, M=None, N=None, K=None,
-             split_bf16=False):
+             split_bf16=False, three_products=False):
         """C = alpha op(A) op(B) + beta C on the matrix cores (complex128 or complex64;
-        split_bf16 with complex64: bf16x3 products with FP32 accumulation)."""
+        split_bf16 with complex64: bf16x3 products with FP32 accumulation; three_products with
+        complex128: each complex product from three real FP64 products)."""
         import torch
         if A.dtype not in (torch.complex128, torch.complex64):
             raise TypeError("gemm takes complex128 or complex64 operands")
         if split_bf16 and A.dtype != torch.complex64:
             raise TypeError("split_bf16 takes complex64 operands")
-        prec = 0 if A.dtype == torch.complex128 else (2 if split_bf16 else 1)
+        if three_products and A.dtype != torch.complex128:
+            raise TypeError("three_products selects the FP64 form (complex128 operands)")
+        prec = (3 if three_products else 0) if A.dtype == torch.complex128 else \
+            (2 if split_bf16 else 1)
         M = C.shape[0] if M is None else M
         N = C.shape[1] if N is None else N
         if K is None:

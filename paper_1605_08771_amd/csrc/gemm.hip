@@ -35,6 +35,7 @@ namespace feast {
 
 thread_local GemmProfiler* g_gemm_prof = nullptr;
 thread_local bool g_split_bf16 = false;
+thread_local bool g_z3m = false;
 
 namespace {
 
@@ -43,11 +44,14 @@ constexpr int BM = 64, BN = 64, BK = 16, NT = 256, PAD = 1;
 // FEAST_GEMM_3M = 1: FP32 complex products as three real matrix-core products (Gauss's
 // method: 3 MFMAs per 16x16x4 complex step instead of 4, a quarter less matrix-core work; the
 // imaginary part is formed as a difference, with a normwise error bound a small multiple of
-// the four-product one).  0: the four-product form.  FP64 tiles keep the four-product form:
-// the third accumulator set does not fit their registers at two waves per SIMD.
+// the four-product one).  0: the four-product form.  FP64 products use the three-product form
+// only inside a Z3mScope (the caller decides where its accuracy suffices); the FP64 tiles then
+// prefetch one K-tile ahead instead of two, since the third accumulator set and the second
+// register set of the deeper pipeline do not both fit at two waves per SIMD.
 #ifndef FEAST_GEMM_3M
 #define FEAST_GEMM_3M 1
 #endif
+
 
 template <typename T>
 struct CT;
@@ -102,7 +106,7 @@ struct Args {
 };
 
 // One output tile of one problem, op(A) = OPA.  (i0, j0) is the tile origin.
-template <typename T, int OPA, int OPB>
+template <typename T, int OPA, int OPB, bool G3>
 __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int prob, int b1,
                                           int b2, int i0, int j0,
                                           typename CT<T>::v2 (*As)[BK][BM + PAD],
@@ -232,7 +236,7 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
           }                                                                           \
       }                                                                               \
   }
-  constexpr bool G3 = FEAST_GEMM_3M && sizeof(T) == 4;
+  constexpr bool PF1 = G3 && sizeof(T) == 8;
   accv accr[2][2], acci[2][2], accs[2][2];
   // A 16 x 16 output block that lies entirely past M or N has nothing to compute; the test
   // is uniform over the wave, so skipping its MFMAs frees the matrix core for other waves.
@@ -248,6 +252,30 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
     }
 
   const int nkt = (K + BK - 1) / BK;
+  if constexpr (PF1) {
+    // prefetch distance one (FP64 with three accumulator sets: the second register set of
+    // the distance-two pipeline does not fit beside them)
+    if (nkt > 0) {
+      FEAST_LOAD_TILE_INTO(0, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)
+      FEAST_STORE_TILE_FROM(0, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)
+    }
+    __syncthreads();
+#define FEAST_KLOOP1(CHK)                                                            \
+  for (int kt = 0; kt < nkt; ++kt) {                                                 \
+    const int cur = kt & 1;                                                          \
+    if (kt + 1 < nkt)                                                                \
+      FEAST_LOAD_TILE_INTO((kt + 1) * BK, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)    \
+    FEAST_COMPUTE(cur, CHK)                                                          \
+    if (kt + 1 < nkt) FEAST_STORE_TILE_FROM(cur ^ 1, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3) \
+    __syncthreads();                                                                 \
+  }
+    if (i0 + BM <= M && j0 + BN <= N) {
+      FEAST_KLOOP1(0)
+    } else {
+      FEAST_KLOOP1(1)
+    }
+#undef FEAST_KLOOP1
+  } else {
   v2 qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3;
   // prefetch distance two: tile kt+2 is in flight while tile kt is multiplied
   if (nkt > 0) {
@@ -276,6 +304,7 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
     FEAST_KLOOP(0)
   } else {
     FEAST_KLOOP(1)
+  }
   }
 #undef FEAST_KLOOP
 #undef FEAST_LOAD_A
@@ -315,7 +344,7 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
       }
 }
 
-template <typename T, int OPA0, int OPA1, int OPB>
+template <typename T, int OPA0, int OPA1, int OPB, bool G3>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void gemm_kernel(const Args<typename CT<T>::v2> a) {
   typedef typename CT<T>::v2 v2;
   __shared__ v2 As[2][BK][BM + PAD];
@@ -337,17 +366,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ge
   const int prob = (int)(rest / a.n2);
   const int i0 = (tile / a.tilesN) * BM, j0 = (tile % a.tilesN) * BN;
   if constexpr (OPA0 == OPA1) {
-    gemm_tile<T, OPA0, OPB>(a, prob, b1, b2, i0, j0, As, Bs);
+    gemm_tile<T, OPA0, OPB, G3>(a, prob, b1, b2, i0, j0, As, Bs);
   } else {
-    if (prob == 0) gemm_tile<T, OPA0, OPB>(a, 0, b1, b2, i0, j0, As, Bs);
-    else gemm_tile<T, OPA1, OPB>(a, 1, b1, b2, i0, j0, As, Bs);
+    if (prob == 0) gemm_tile<T, OPA0, OPB, G3>(a, 0, b1, b2, i0, j0, As, Bs);
+    else gemm_tile<T, OPA1, OPB, G3>(a, 1, b1, b2, i0, j0, As, Bs);
   }
 }
 
 template <typename T, int OPA0, int OPA1, int OPB>
 void launch(hipStream_t s, const Args<typename CT<T>::v2>& a, int nprob) {
   dim3 grid(a.tilesM * a.tilesN, a.n1, a.n2 * nprob);
-  hipLaunchKernelGGL((gemm_kernel<T, OPA0, OPA1, OPB>), grid, dim3(NT), 0, s, a);
+  if constexpr (sizeof(T) == 4) {
+    hipLaunchKernelGGL((gemm_kernel<T, OPA0, OPA1, OPB, (bool)FEAST_GEMM_3M>), grid, dim3(NT), 0,
+                       s, a);
+  } else if (g_z3m) {
+    hipLaunchKernelGGL((gemm_kernel<T, OPA0, OPA1, OPB, true>), grid, dim3(NT), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((gemm_kernel<T, OPA0, OPA1, OPB, false>), grid, dim3(NT), 0, s, a);
+  }
 }
 
 template <typename T>
@@ -738,7 +774,8 @@ int zgemm_resident_tiles() {
   int cus = 0, per_cu = 0;
   FEAST_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   FEAST_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, reinterpret_cast<const void*>(&gemm_kernel<double, OP_N, OP_N, OP_N>), NT, 0));
+      &per_cu, reinterpret_cast<const void*>(&gemm_kernel<double, OP_N, OP_N, OP_N, false>), NT,
+      0));
   const int r = std::max(1, cus * std::max(1, per_cu));
   if (c) c->store(r);
   return r;

@@ -18,7 +18,7 @@ extern "C" int feast_kern_gemm(int prec, int opA, int opB, int M, int N, int K,
                                const double* alpha, const void* A, long lda, const void* B,
                                long ldb, const double* beta, void* C, long ldc,
                                void* hip_stream) {
-  if (prec < 0 || prec > 2) return -1;
+  if (prec < 0 || prec > 3) return -1;
   if (opA < 0 || opA > 2) return -2;
   if (opB < 0 || opB > 2) return -3;
   if (M < 0) return -4;
@@ -34,10 +34,11 @@ extern "C" int feast_kern_gemm(int prec, int opA, int opB, int M, int N, int K,
   if (ldc < M || ldc < 1) return -14;
   try {
     hipStream_t s = (hipStream_t)hip_stream;
-    if (prec == 0)
+    if (prec == 0 || prec == 3) {
+      Z3mScope z3(prec == 3);
       zgemm(s, opA, opB, M, N, K, zmake(alpha[0], alpha[1]), (const zd*)A, lda, (const zd*)B, ldb,
             zmake(beta[0], beta[1]), (zd*)C, ldc);
-    else {
+    } else {
       SplitBf16Scope split(prec == 2);
       cgemm(s, opA, opB, M, N, K, make_float2((float)alpha[0], (float)alpha[1]), (const zf*)A,
             lda, (const zf*)B, ldb, make_float2((float)beta[0], (float)beta[1]), (zf*)C, ldc);

@@ -34,6 +34,18 @@ struct SplitBf16Scope {
   ~SplitBf16Scope() { g_split_bf16 = saved; }
 };
 
+// When set (per thread), complex FP64 products (zgemm, zgemm_pair, zgemm_nn_split) run as
+// three real MFMA products (Re Re, Im Im, (Re + Im)(Re + Im)) instead of four: a quarter less
+// matrix-core work, with a normwise error bound a few times the four-product one.  The
+// Rayleigh-Ritz step sets it; the factorization and the sweeps, whose errors set the FP64
+// residual floor, do not.  FP32 products always use the three-product form.
+extern thread_local bool g_z3m;
+struct Z3mScope {
+  bool saved;
+  explicit Z3mScope(bool on) : saved(g_z3m) { g_z3m = on; }
+  ~Z3mScope() { g_z3m = saved; }
+};
+
 // C = alpha op(A) op(B) + beta C (column-major, complex; FP64 or FP32 matrix cores).
 void zgemm(hipStream_t s, int opA, int opB, int M, int N, int K, zd alpha, const zd* A, long lda,
            const zd* B, long ldb, zd beta, zd* C, long ldc, const Batch& bt = Batch());

@@ -145,7 +145,7 @@ def test_solve_argument_checks():
 def test_kernel_api_argument_checks():
     L = fm.lib()
     al = ctypes.cast((ctypes.c_double * 2)(1.0, 0.0), ctypes.POINTER(ctypes.c_double))
-    assert L.feast_kern_gemm(3, 0, 0, 4, 4, 4, al, DEV, 4, DEV, 4, al, DEV, 4, None) == -1
+    assert L.feast_kern_gemm(4, 0, 0, 4, 4, 4, al, DEV, 4, DEV, 4, al, DEV, 4, None) == -1
     assert L.feast_kern_gemm(0, 5, 0, 4, 4, 4, al, DEV, 4, DEV, 4, al, DEV, 4, None) == -2
     assert L.feast_kern_gemm(0, 0, 0, 4, 4, 4, al, DEV, 3, DEV, 4, al, DEV, 4, None) == -9
     npo = ctypes.c_int()

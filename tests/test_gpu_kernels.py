@@ -34,11 +34,13 @@ def _crand(rng, *shape):
 OPS = {0: lambda a: a, 1: lambda a: a.T, 2: lambda a: a.conj().T}
 
 
+@pytest.mark.parametrize("three", [False, True])
 @pytest.mark.parametrize("opA", [0, 1, 2])
 @pytest.mark.parametrize("opB", [0, 1, 2])
 @pytest.mark.parametrize("shape", [(1, 1, 1), (17, 5, 33), (64, 64, 16), (130, 77, 70),
                                    (65, 129, 0), (200, 31, 257)])
-def test_zgemm_fp64(fe, opA, opB, shape):
+def test_zgemm_fp64(fe, opA, opB, shape, three):
+    """Four-product and three-product (factorization, Rayleigh-Ritz) FP64 forms."""
     import torch
     M, N, K = shape
     rng = np.random.default_rng(M * 1000 + N * 10 + K + 7 * opA + opB)
@@ -48,7 +50,7 @@ def test_zgemm_fp64(fe, opA, opB, shape):
     alpha, beta = 0.7 - 0.3j, -1.1 + 0.4j
     ref = alpha * OPS[opA](A) @ OPS[opB](B) + beta * C
     dA, dB, dC = _dev(A), _dev(B), _dev(C)
-    st = fe.gemm(opA, opB, dA, dB, dC, alpha, beta, M=M, N=N, K=K)
+    st = fe.gemm(opA, opB, dA, dB, dC, alpha, beta, M=M, N=N, K=K, three_products=three)
     torch.cuda.synchronize()
     assert st == 0
     got = dC.cpu().numpy()
