@@ -95,6 +95,9 @@ struct LuWork {
   int* perm = nullptr;      // nc * np, P as a row gather: (P X)[r] = X[perm[r]]
   int* pinv = nullptr;      // nc * np, inverse of perm
   int* flag = nullptr;      // 1 int: set to 1 + column of the first exact zero pivot
+  void* linv = nullptr;     // 8 * nc * 64 * 64 complex: inverses of the L11 blocks of the
+                            // current outer panel's sub-panels
+  void* u12 = nullptr;      // nc * 64 * np complex: staging copy of the panel's rows of A12
 };
 size_t lu_work_bytes(int np, int nc);
 void lu_work_carve(LuWork& w, void* base, int np, int nc);

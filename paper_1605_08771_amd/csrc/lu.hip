@@ -12,7 +12,8 @@
 //          panel's later columns and a second one writes the group's rows of U there.
 //   swaps: the panel's pivot rows are moved to the top with the fewest row moves (at most
 //          2 x 64 rows, LAPACK swap order) over all columns, and the permutation is updated;
-//   U12:   unit-lower triangular solve with the 64x64 L11 staged in LDS;
+//   U12:   L11^{-1} A12 as one matrix-core product with the explicit inverse of the unit-lower
+//          64x64 L11 (formed once per panel in LDS);
 //   A22 -= L21 U12 on the matrix cores (batched complex GEMM).
 #include "common.h"
 #include "kernels.h"
@@ -437,42 +438,50 @@ __global__ __launch_bounds__(256) void laswp_kernel(typename V2<T>::t* __restric
   }
 }
 
-// U12 = L11^{-1} A12 for 64 columns per workgroup (L11 unit lower, staged in LDS).
+// Inverse of the unit-lower w x w diagonal block L11 of the panel at column k (w <= 64) for
+// every node (one workgroup per node), into Linv (64 x 64 per node, ld 64; identity past w):
+// forward substitution on the identity in LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void trsm_u12_kernel(typename V2<T>::t* __restrict__ M, int np,
-                                                       int k, int w, int c0, int c1) {
+__global__ __launch_bounds__(256) void l11_inverse_kernel(const typename V2<T>::t* __restrict__ M,
+                                                          int np, int k, int w,
+                                                          typename V2<T>::t* __restrict__ Linv) {
   typedef typename V2<T>::t v2;
   __shared__ v2 L[NBP][NBP + 1];
   __shared__ v2 X[NBP][NBP + 1];
-  const int node = blockIdx.y;
-  M += (long)node * np * np;
+  const int node = blockIdx.x;
   const int t = threadIdx.x;
-  const int col0 = c0 + blockIdx.x * 64;
-  for (int e = t; e < w * w; e += 256) {
-    int r = e % w, cc = e / w;
-    L[r][cc] = M[k + r + (long)(k + cc) * np];
-  }
-  for (int e = t; e < w * 64; e += 256) {
-    int r = e % w, cc = e / w;
-    int gc = col0 + cc;
-    X[r][cc] = (gc < c1) ? M[k + r + (long)gc * np] : v2{0, 0};
+  M += (long)node * np * np;
+  for (int e = t; e < NBP * NBP; e += 256) {
+    const int r = e % NBP, c = e / NBP;
+    L[r][c] = (r < w && c < w && r > c) ? M[k + r + (long)(k + c) * np] : v2{0, 0};
+    X[r][c] = v2{T(r == c ? 1 : 0), T(0)};
   }
   __syncthreads();
-  for (int r = 0; r < w - 1; ++r) {
-    int rows = w - 1 - r;
-    for (int e = t; e < rows * 64; e += 256) {
-      int i = r + 1 + e % rows, cc = e / rows;
-      v2 l = L[i][r], x = X[r][cc];
-      X[i][cc].x -= l.x * x.x - l.y * x.y;
-      X[i][cc].y -= l.x * x.y + l.y * x.x;
+  for (int r = 0; r < NBP - 1; ++r) {  // row i -= L[i][r] * row r, for i > r (columns c <= r)
+    const int rows = NBP - 1 - r;
+    for (int e = t; e < rows * (r + 1); e += 256) {
+      const int i = r + 1 + e % rows, c = e / rows;
+      const v2 l = L[i][r], x = X[r][c];
+      X[i][c].x -= l.x * x.x - l.y * x.y;
+      X[i][c].y -= l.x * x.y + l.y * x.x;
     }
     __syncthreads();
   }
-  for (int e = t; e < w * 64; e += 256) {
-    int r = e % w, cc = e / w;
-    int gc = col0 + cc;
-    if (gc < c1) M[k + r + (long)gc * np] = X[r][cc];
-  }
+  v2* out = Linv + (long)node * NBP * NBP;
+  for (int e = t; e < NBP * NBP; e += 256) out[e] = X[e % NBP][e / NBP];
+}
+
+// Staging copy of the panel's rows k .. k+w-1 of columns c0 .. c1-1 into U (ld 64 per node).
+template <typename T>
+__global__ void rows_copy_kernel(const typename V2<T>::t* __restrict__ M, int np, int k, int w,
+                                 int c0, int c1, typename V2<T>::t* __restrict__ U) {
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long cols = c1 - c0;
+  if (idx >= (long)NBP * cols) return;
+  const int node = blockIdx.y;
+  const int r = (int)(idx % NBP), c = (int)(idx / NBP);
+  if (r >= w) return;
+  U[(long)node * NBP * np + r + (long)c * NBP] = M[(long)node * np * np + k + r + (c0 + c) * (long)np];
 }
 
 __global__ void perm_init_kernel(int* perm, int np, int nc) {
@@ -485,6 +494,18 @@ __global__ void perm_invert_kernel(const int* perm, int* pinv, int np, int nc) {
     long node = idx / np;
     pinv[node * np + perm[idx]] = (int)(idx % np);
   }
+}
+
+// C = ar op(A) op(B) + br C in the factor precision.
+template <typename T>
+void gemm_t(hipStream_t s, int opA, int opB, int M, int N, int K, double ar,
+            const typename V2<T>::t* A, long lda, const typename V2<T>::t* B, long ldb, double br,
+            typename V2<T>::t* C, long ldc, const Batch& bt) {
+  if constexpr (sizeof(T) == 8)
+    zgemm(s, opA, opB, M, N, K, zmake(ar, 0), A, lda, B, ldb, zmake(br, 0), C, ldc, bt);
+  else
+    cgemm(s, opA, opB, M, N, K, make_float2((float)ar, 0), A, lda, B, ldb,
+          make_float2((float)br, 0), C, ldc, bt);
 }
 
 // M[r0:r0+rows, c0:c0+cols] -= M[r0:r0+rows, k:k+kw] * M[k:k+kw, c0:c0+cols] for every node.
@@ -554,11 +575,30 @@ void lu_factor(hipStream_t s, typename V2<T>::t* M, int np, int nc, LuWork& w) {
                        0, s, M, np, w.moves);
     FEAST_LAUNCH_CHECK();
   };
-  // U12 = L11^{-1} M[kp:kp+width, c0:c1] with the unit-lower diagonal block of panel kp.
-  auto trsm = [&](int kp, int width, int c0, int c1) {
-    hipLaunchKernelGGL((trsm_u12_kernel<T>), dim3((c1 - c0 + 63) / 64, nc), dim3(256), 0, s, M,
-                       np, kp, width, c0, c1);
+  // U12 = L11^{-1} M[kp:kp+width, c0:c1] with the unit-lower diagonal block of panel kp: the
+  // block's explicit inverse (computed once per panel, l11_inverse) times a staging copy of the
+  // rows, one matrix-core product over all nodes.
+  typedef typename V2<T>::t v2;
+  v2* u12 = (v2*)w.u12;
+  // inverse of sub-panel q's L11 (q < NSUB within the current outer panel)
+  auto linv = [&](int q) { return (v2*)w.linv + (long)q * nc * NBP * NBP; };
+  auto l11_inverse = [&](int q, int kp, int width) {
+    hipLaunchKernelGGL((l11_inverse_kernel<T>), dim3(nc), dim3(256), 0, s, M, np, kp, width,
+                       linv(q));
     FEAST_LAUNCH_CHECK();
+  };
+  auto trsm = [&](int q, int kp, int width, int c0, int c1) {
+    const long tot = (long)NBP * (c1 - c0);
+    hipLaunchKernelGGL((rows_copy_kernel<T>), dim3((unsigned)((tot + 255) / 256), nc), dim3(256),
+                       0, s, M, np, kp, width, c0, c1, u12);
+    FEAST_LAUNCH_CHECK();
+    Batch b;
+    b.n1 = nc;
+    b.sA1 = (long)NBP * NBP;
+    b.sB1 = (long)NBP * np;
+    b.sC1 = (long)np * np;
+    gemm_t<T>(s, OP_N, OP_N, width, c1 - c0, width, 1.0, linv(q), NBP, u12, NBP, 0.0,
+              M + kp + (long)c0 * np, np, b);
   };
   // Outer panels of NSUB 64-wide sub-panels: the trailing update then contracts over
   // NSUB * 64 columns at once (1 / NSUB of the read-modify-write traffic of 64-deep updates).
@@ -575,15 +615,16 @@ void lu_factor(hipStream_t s, typename V2<T>::t* M, int np, int nc, LuWork& w) {
     for (int q = 0, kq = k; q < NSUB && kw[q] > 0; kq += kw[q], ++q) {
       factor_panel(kq, kw[q]);
       const int e = kq + kw[q];  // first column of the outer panel not yet factored
+      if (e < np) l11_inverse(q, kq, kw[q]);
       if (e < k + W) {
-        trsm(kq, kw[q], e, k + W);
+        trsm(q, kq, kw[q], e, k + W);
         gemm_update<T>(s, M, np, nc, e, np - e, e, k + W - e, kq, kw[q]);
       }
     }
     const int c = k + W;
     if (c < np) {
       for (int q = 0, kq = k; q < NSUB && kw[q] > 0; kq += kw[q], ++q) {
-        trsm(kq, kw[q], c, np);
+        trsm(q, kq, kw[q], c, np);
         const int e = kq + kw[q];
         if (e < c) gemm_update<T>(s, M, np, nc, e, c - e, c, np - c, kq, kw[q]);
       }
@@ -608,7 +649,9 @@ size_t lu_work_bytes(int np, int nc) {
   b += sizeof(int) * (size_t)nc * (4 * NBP + 1); // moves
   b += 2 * sizeof(int) * (size_t)nc * np;        // perm, pinv
   b += 256;                                      // flag
-  return b + 8 * 256;                            // alignment slack
+  b += sizeof(double2) * (size_t)nc * NSUB * NBP * NBP;  // L11 inverses (FP64 size)
+  b += sizeof(double2) * (size_t)nc * NBP * np;  // U12 staging
+  return b + 10 * 256;                           // alignment slack
 }
 
 void lu_work_carve(LuWork& w, void* base, int np, int nc) {
@@ -627,6 +670,8 @@ void lu_work_carve(LuWork& w, void* base, int np, int nc) {
   w.perm = (int*)take(sizeof(int) * (size_t)nc * np);
   w.pinv = (int*)take(sizeof(int) * (size_t)nc * np);
   w.flag = (int*)take(256);
+  w.linv = take(sizeof(double2) * (size_t)nc * NSUB * NBP * NBP);
+  w.u12 = take(sizeof(double2) * (size_t)nc * NBP * np);
 }
 
 void shift_matrices(hipStream_t s, const void* A, long lda, int is_real, int n, int np,

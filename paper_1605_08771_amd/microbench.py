@@ -2,6 +2,7 @@
 
     python -m paper_1605_08771_amd.microbench gemm --prec fp64 --shape 61440 300 512 --reps 4
     python -m paper_1605_08771_amd.microbench jacobi --m 300 --kind random --reps 3
+    python -m paper_1605_08771_amd.microbench filter --n 32768 --m0 768 --prec fp32ir
 
 `gemm` runs C = -op(A) op(B) + C through `feast_kern_gemm` (prec fp64, fp32 or bf16x3) on
 seeded Gaussian operands (one untimed call first, then `rounds` rounds of `reps` timed ones,
@@ -98,6 +99,27 @@ def _jacobi(a):
     f.close()
 
 
+def _filter(a):
+    """One filter application (feast_filter_apply) on a seeded random Hermitian matrix of
+    order n with an m0-column block: the launch shapes of that workload's factorization and
+    sweeps (the values do not change them).  Prints the phase times of the call."""
+    import torch
+    import paper_1605_08771_amd as fm
+    g = torch.Generator(device="cuda").manual_seed(a.seed)
+    n, m0 = a.n, a.m0
+    A = torch.randn((n, n), dtype=torch.complex128, device="cuda", generator=g)
+    A = (A + A.mH) * (0.5 / n ** 0.5)
+    A = fm.fortran(A)
+    X = fm.fortran(torch.randn((n, m0), dtype=torch.complex128, device="cuda", generator=g))
+    f = fm.Feast()
+    prec = {"fp64": 0, "fp32ir": 1, "bf16x3ir": 2}[a.prec]
+    st, Q = f.filter_apply(A, X, -0.05, 0.05, a.nc, prec=prec)
+    torch.cuda.synchronize()
+    print(f"filter n={n} m0={m0} n_c={a.nc} {a.prec}: status {st}, phases {f.timings()}",
+          flush=True)
+    f.close()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -117,8 +139,14 @@ def main(argv=None):
     j.add_argument("--kind", choices=["random", "gram"], default="random")
     j.add_argument("--reps", type=int, default=3)
     j.add_argument("--seed", type=int, default=0)
+    fl = sub.add_parser("filter")
+    fl.add_argument("--n", type=int, required=True)
+    fl.add_argument("--m0", type=int, required=True)
+    fl.add_argument("--nc", type=int, default=8)
+    fl.add_argument("--prec", choices=["fp64", "fp32ir", "bf16x3ir"], default="fp32ir")
+    fl.add_argument("--seed", type=int, default=0)
     a = ap.parse_args(argv)
-    (_gemm if a.what == "gemm" else _jacobi)(a)
+    {"gemm": _gemm, "jacobi": _jacobi, "filter": _filter}[a.what](a)
 
 
 if __name__ == "__main__":
