@@ -4,7 +4,8 @@
     python -m paper_1605_08771_amd.microbench jacobi --m 300 --kind random --reps 3
     python -m paper_1605_08771_amd.microbench filter --n 32768 --m0 768 --prec fp32ir
 
-`gemm` runs C = -op(A) op(B) + C through `feast_kern_gemm` (prec fp64, fp32 or bf16x3) on
+`gemm` runs C = -op(A) op(B) + C through `feast_kern_gemm` (prec fp64, fp64x3 (three real
+FP64 products per complex one), fp32 or bf16x3) on
 seeded Gaussian operands (one untimed call first, then `rounds` rounds of `reps` timed ones,
 the fastest round reported; a counter run with one round sees reps + 1 dispatches); with
 `--vendor` it also times the same product through torch.addmm (the ROCm BLAS libraries, fp64
@@ -21,7 +22,7 @@ import sys
 def _gemm(a):
     import torch
     import paper_1605_08771_amd as fm
-    dt = torch.complex128 if a.prec == "fp64" else torch.complex64
+    dt = torch.complex128 if a.prec in ("fp64", "fp64x3") else torch.complex64
     M, N, K = a.shape
     g = torch.Generator(device="cuda").manual_seed(a.seed)
 
@@ -36,7 +37,8 @@ def _gemm(a):
     split = a.prec == "bf16x3"
 
     def ours():
-        st = f.gemm(a.opA, a.opB, A, B, C, -1.0, 1.0, M=M, N=N, K=K, split_bf16=split)
+        st = f.gemm(a.opA, a.opB, A, B, C, -1.0, 1.0, M=M, N=N, K=K, split_bf16=split,
+                    three_products=a.prec == "fp64x3")
         if st != 0:
             raise SystemExit(f"feast_kern_gemm returned {st}")
 
@@ -125,7 +127,7 @@ def main(argv=None):
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="what", required=True)
     g = sub.add_parser("gemm")
-    g.add_argument("--prec", choices=["fp64", "fp32", "bf16x3"], default="fp64")
+    g.add_argument("--prec", choices=["fp64", "fp64x3", "fp32", "bf16x3"], default="fp64")
     g.add_argument("--shape", type=int, nargs=3, metavar=("M", "N", "K"), required=True)
     g.add_argument("--opA", type=int, default=0, choices=[0, 1, 2])
     g.add_argument("--opB", type=int, default=0, choices=[0, 1, 2])
