@@ -32,8 +32,10 @@ int feast_kern_gemm(int prec, int opA, int opB, int M, int N, int K, const doubl
  * (ld np, complex128 for prec 0, complex64 for prec 1 and 2; the trailing updates are
  * four-product FP64 (prec 0) or three-product FP32 (prec 1) products, or bf16x3 products
  * (prec 2), see feast_kern_gemm) receiving unit-lower L and U; perm:
- * nc blocks of np ints with (P M)[r] = M[perm[r]].  Synchronises the stream; returns 6 on an
- * exact zero pivot. */
+ * nc blocks of np ints with (P M)[r] = M[perm[r]].  prec + 8: the same factorization with
+ * one launch per panel column throughout (the solver runs a panel's column groups as single
+ * launches once few rows remain; both schedules give bit-identical factors).  Synchronises
+ * the stream; returns 6 on an exact zero pivot. */
 int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, const double* z, void* LU,
                   int* perm, int* np_out, void* hip_stream);
 

@@ -454,10 +454,11 @@ class Feast:
                                    _vp(self._stream.cuda_stream))
         return st
 
-    def lu(self, A, z, prec=0):
+    def lu(self, A, z, prec=0, column_steps=False):
         """Factors of z_j I - A for the nodes z (numpy complex array); prec 0 FP64, 1 FP32,
-        2 FP32 with bf16x3 trailing updates.  Returns (status, LU [nc, np, np] tensor in
-        column-major blocks, perm [nc, np])."""
+        2 FP32 with bf16x3 trailing updates; column_steps: one launch per panel column
+        throughout (the reference schedule of the short-panel groups).  Returns (status,
+        LU [nc, np, np] tensor in column-major blocks, perm [nc, np])."""
         import numpy as np
         import torch
         _need(A, "A", torch.complex128)
@@ -472,7 +473,8 @@ class Feast:
         dt = torch.complex128 if prec == 0 else torch.complex64
         LU = torch.empty((nc, np_, np_), dtype=dt, device=A.device)
         perm = torch.empty((nc, np_), dtype=torch.int32, device=A.device)
-        st = lib().feast_kern_lu(prec, _vp(A.data_ptr()), lda, n, nc, zz.ctypes.data_as(_dp),
+        st = lib().feast_kern_lu(prec | (8 if column_steps else 0), _vp(A.data_ptr()), lda, n,
+                                 nc, zz.ctypes.data_as(_dp),
                                  _vp(LU.data_ptr()), ctypes.cast(ctypes.c_void_p(perm.data_ptr()), _ip),
                                  None, _vp(self._stream.cuda_stream))
         # blocks are column-major: element (r, c) of node j at LU[j].flatten()[r + c*np]

@@ -51,6 +51,8 @@ extern "C" int feast_kern_gemm(int prec, int opA, int opB, int M, int N, int K,
 
 extern "C" int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, const double* z,
                              void* LU, int* perm, int* np_out, void* hip_stream) {
+  const bool column_steps = prec >= 0 && (prec & 8);
+  if (column_steps) prec &= 7;
   if (prec < 0 || prec > 2) return -1;
   if (n < 1) return -4;
   if (!A) return -2;
@@ -70,6 +72,7 @@ extern "C" int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, co
     FEAST_HIP(hipMalloc(&wbuf, lu_work_bytes(np, nc)));
     LuWork w;
     lu_work_carve(w, wbuf, np, nc);
+    w.column_steps = column_steps;
     if (prec == 0) {
       shift_matrices(s, A, lda, 0, n, np, zdev, nc, (zd*)LU, w.flag);
       lu_factor_f64(s, (zd*)LU, np, nc, w);

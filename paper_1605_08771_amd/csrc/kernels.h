@@ -98,6 +98,8 @@ struct LuWork {
   void* linv = nullptr;     // 8 * nc * 64 * 64 complex: inverses of the L11 blocks of the
                             // current outer panel's sub-panels
   void* u12 = nullptr;      // nc * 64 * np complex: staging copy of the panel's rows of A12
+  bool column_steps = false;  // one launch per panel column throughout (no short-panel
+                              // groups); the same factors, a reference schedule for tests
 };
 size_t lu_work_bytes(int np, int nc);
 void lu_work_carve(LuWork& w, void* base, int np, int nc);

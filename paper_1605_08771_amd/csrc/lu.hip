@@ -3,7 +3,8 @@
 // independent, so all n_c factorizations advance together in every launch).
 //
 // Blocked right-looking LU, panel width 64:
-//   panel: one launch per column.  Rows are never moved inside the panel ("implicit"
+//   panel: one launch per column (one per group of PG columns while at most 1024 (FP64) or
+//          2048 (FP32) rows remain).  Rows are never moved inside the panel ("implicit"
 //          pivoting): each launch reduces the per-workgroup pivot candidates of the previous
 //          launch, reads the pivot row, and eliminates every other active row, then leaves
 //          the candidates of the next column.  The pivot row is read-only in that launch, so
@@ -344,6 +345,142 @@ __global__ __launch_bounds__(RPW) void panel_group_pivots_kernel(
   }
 }
 
+// Short panels (at most GT * R rows from the panel start down): one workgroup per node runs
+// all column steps of a group in one launch, its rows of the group's columns held in
+// registers (thread t owns rows k + t + i GT, i < R).  The arithmetic and the pivot choice
+// (largest |.|^2, ties to the lower row) are those of panel_step_kernel, so the factors are
+// the same; a group costs one launch instead of one per column.  Per column each wave reduces
+// its candidates with lane shuffles and leaves its best row's group values in LDS; after one
+// barrier every thread reduces the per-wave candidates itself and reads the pivot row from
+// the winning wave's slot.  The slots alternate between columns, so that one barrier per
+// column orders every LDS write after the reads of two columns before.
+template <typename T>
+struct ShortPanel;
+template <>
+struct ShortPanel<float> {
+  static constexpr int R = 2;
+};
+template <>
+struct ShortPanel<double> {
+  static constexpr int R = 1;
+};
+constexpr int GT = 1024;     // threads of the short-panel kernel
+constexpr int GW = GT / 64;  // its waves
+
+template <typename T>
+__global__ __launch_bounds__(GT) void panel_group_short_kernel(
+    typename V2<T>::t* __restrict__ M, int np, int k, int g0, int gend, int* __restrict__ retired,
+    int* __restrict__ pivrows, int* flag) {
+  typedef typename V2<T>::t v2;
+  constexpr int R = ShortPanel<T>::R;
+  __shared__ double sv[2][GW];
+  __shared__ int sr[2][GW];
+  __shared__ v2 srow[2][GW][PG];  // each wave's best row in the group's columns
+  __shared__ v2 zrow[PG];         // pivot row after an exactly zero column
+  const int node = blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  M += (long)node * np * np;
+  retired += node * np;
+  const int stamp = k + 1;
+  const int ng = gend - g0;
+  v2 x[R][PG];
+  bool act[R];
+  int row[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    row[i] = k + t + i * GT;
+    const bool ok = row[i] < np;
+    act[i] = ok && retired[row[i]] != stamp;
+#pragma unroll
+    for (int q = 0; q < PG; ++q)
+      x[i][q] = (ok && q < ng) ? M[row[i] + (long)(k + g0 + q) * np] : v2{0, 0};
+  }
+  for (int j = 0; j < ng; ++j) {
+    const int b = j & 1;
+    double v = -1.0;
+    int r = 0x7fffffff;
+    v2 xj[R];  // column j of the owned rows
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      xj[i] = x[i][0];
+#pragma unroll
+      for (int q = 1; q < PG; ++q)
+        if (q == j) xj[i] = x[i][q];
+      if (act[i]) argmax_merge(v, r, (double)xj[i].x * xj[i].x + (double)xj[i].y * xj[i].y, row[i]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(v, off);
+      const int orow = __shfl_xor(r, off);
+      argmax_merge(v, r, ov, orow);
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if (act[i] && row[i] == r) {
+#pragma unroll
+        for (int q = 0; q < PG; ++q) srow[b][wave][q] = x[i][q];
+      }
+    if (lane == 0) {
+      sv[b][wave] = v;
+      sr[b][wave] = r;
+    }
+    __syncthreads();
+    double bv = -1.0;
+    int br = 0x7fffffff, bw = 0;
+    for (int w2 = 0; w2 < GW; ++w2) {
+      const double ov = sv[b][w2];
+      const int orow = sr[b][w2];
+      if (ov > bv || (ov == bv && orow < br)) {
+        bv = ov;
+        br = orow;
+        bw = w2;
+      }
+    }
+    const int c = k + g0 + j;
+    const bool bad = !(bv > 0.0) || br < k || br >= np;  // zero column or non-finite values
+    const int p = bad ? c : br;
+    const v2* u = srow[b][bw];
+    if (bad) {  // uniform: the pivot row is row c, owned by thread c - k
+      if (t == c - k) {
+#pragma unroll
+        for (int q = 0; q < PG; ++q) zrow[q] = x[0][q];
+      }
+      __syncthreads();
+      u = zrow;
+    }
+    const v2 rinv = bad ? v2{0, 0} : crecip(u[j]);
+    if (t == 0) {
+      pivrows[node * NBP + g0 + j] = p;
+      if (bad && flag) atomicCAS(flag, 0, c + 1);
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (row[i] == p) {
+        act[i] = false;
+        retired[p] = stamp;
+      }
+      if (act[i]) {
+        const v2 l = cmul(xj[i], rinv);
+#pragma unroll
+        for (int q = 0; q < PG; ++q) {
+          if (q == j) x[i][q] = l;
+          if (q > j && q < ng) {
+            const v2 uq = u[q];
+            x[i][q].x -= l.x * uq.x - l.y * uq.y;
+            x[i][q].y -= l.x * uq.y + l.y * uq.x;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+#pragma unroll
+    for (int q = 0; q < PG; ++q)
+      if (row[i] < np && q < ng) M[row[i] + (long)(k + g0 + q) * np] = x[i][q];
+  }
+}
+
 // One workgroup per node: the LAPACK-order swap sequence of the panel, simulated on the set
 // of affected positions (the panel's top rows and the pivot rows below them), gives a list
 // of row moves (dst <- src) and the same moves applied to perm.  Slots: position k + i is
@@ -545,18 +682,27 @@ void lu_factor(hipStream_t s, typename V2<T>::t* M, int np, int nc, LuWork& w) {
   // steps, row moves applied across all columns).
   auto factor_panel = [&](int kp, int width) {
     const int nwg = (np - kp + RPW - 1) / RPW;
+    const bool short_panel = !w.column_steps && np - kp <= GT * ShortPanel<T>::R;
     double* pv[2] = {w.pval, w.pval + nc * maxwg};
     int* pr[2] = {w.prow, w.prow + nc * maxwg};
-    hipLaunchKernelGGL((panel_search_kernel<T>), dim3(nwg, nc), dim3(RPW), 0, s, M, np, kp, pv[0],
-                       pr[0], maxwg);
-    FEAST_LAUNCH_CHECK();
+    if (!short_panel) {
+      hipLaunchKernelGGL((panel_search_kernel<T>), dim3(nwg, nc), dim3(RPW), 0, s, M, np, kp,
+                         pv[0], pr[0], maxwg);
+      FEAST_LAUNCH_CHECK();
+    }
     for (int g0 = 0; g0 < width; g0 += PG) {
       const int gend = std::min(width, g0 + PG);
-      for (int jj = g0; jj < gend; ++jj) {
-        hipLaunchKernelGGL((panel_step_kernel<T>), dim3(nwg, nc), dim3(RPW), 0, s, M, np, kp,
-                           width, jj, gend, nwg, maxwg, pv[jj & 1], pr[jj & 1], pv[(jj + 1) & 1],
-                           pr[(jj + 1) & 1], w.retired, w.pivrows, w.flag);
+      if (short_panel) {
+        hipLaunchKernelGGL((panel_group_short_kernel<T>), dim3(nc), dim3(GT), 0, s, M, np, kp,
+                           g0, gend, w.retired, w.pivrows, w.flag);
         FEAST_LAUNCH_CHECK();
+      } else {
+        for (int jj = g0; jj < gend; ++jj) {
+          hipLaunchKernelGGL((panel_step_kernel<T>), dim3(nwg, nc), dim3(RPW), 0, s, M, np, kp,
+                             width, jj, gend, nwg, maxwg, pv[jj & 1], pr[jj & 1],
+                             pv[(jj + 1) & 1], pr[(jj + 1) & 1], w.retired, w.pivrows, w.flag);
+          FEAST_LAUNCH_CHECK();
+        }
       }
       if (gend < width) {  // later panel columns: the group's rank-PG update, then its U rows
         hipLaunchKernelGGL((panel_group_kernel<T>), dim3(nwg, nc), dim3(RPW), 0, s, M, np, kp,

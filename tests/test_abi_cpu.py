@@ -153,6 +153,12 @@ def test_kernel_api_argument_checks():
     assert L.feast_kern_lu(0, DEV, 500, 500, 1, ctypes.cast(z, ctypes.POINTER(ctypes.c_double)),
                            None, None, ctypes.byref(npo), None) == 0
     assert npo.value == 512
+    zp = ctypes.cast(z, ctypes.POINTER(ctypes.c_double))
+    for prec in (8, 9, 10):  # + 8: one launch per panel column (same factors)
+        assert L.feast_kern_lu(prec, DEV, 500, 500, 1, zp, None, None, ctypes.byref(npo), None) == 0
+    for prec in (3, 11, 16, -1):
+        assert L.feast_kern_lu(prec, DEV, 500, 500, 1, zp, None, None, ctypes.byref(npo),
+                               None) == -1
     assert L.feast_kern_jacobi(None, 4, None, None, None) == -1
 
 

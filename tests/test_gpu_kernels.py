@@ -191,6 +191,25 @@ def test_batched_lu(fe, n, prec):
         assert be < 5.0, (j, be)
 
 
+@pytest.mark.parametrize("n,prec", [(60, 0), (300, 0), (1100, 0), (1500, 1), (2100, 1),
+                                    (700, 2), (2100, 2)])
+def test_short_panel_groups_match_column_steps(fe, n, prec):
+    """The short-panel path (a group of column steps per launch once at most 1024 (FP64) or
+    2048 (FP32) rows remain) gives bit-identical factors and permutations to one launch per
+    column; n = 1100 (FP64) and 2100 (FP32) start with long panels and end with short ones."""
+    import torch
+    rng = np.random.default_rng(n + 7 * prec)
+    G = _crand(rng, n, n)
+    A = 0.5 * (G + G.conj().T) / np.sqrt(n)
+    z = np.array([0.1 + 0.05j, -0.3 + 0.001j, 0.7 + 0.4j])
+    st1, LU1, p1 = fe.lu(_dev(A), z, prec=prec)
+    st2, LU2, p2 = fe.lu(_dev(A), z, prec=prec, column_steps=True)
+    torch.cuda.synchronize()
+    assert st1 == 0 and st2 == 0
+    assert torch.equal(p1, p2)
+    assert torch.equal(torch.view_as_real(LU1.contiguous()), torch.view_as_real(LU2.contiguous()))
+
+
 @pytest.mark.parametrize("m", [1, 2, 7, 31, 33, 64, 75, 301, 512, 513, 900])
 def test_jacobi_vs_lapack(fe, m):
     import torch
