@@ -39,6 +39,13 @@ int feast_kern_gemm(int prec, int opA, int opB, int M, int N, int K, const doubl
 int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, const double* z, void* LU,
                   int* perm, int* np_out, void* hip_stream);
 
+/* Tuning hook for the block triangular sweeps of the Sec. 1 linear solves: every later
+ * factorization (and its solves) uses sweep blocks of nbt rows (64, 128, 256 or 512) and pads
+ * the factors to a multiple of nbt; nbt = 0 restores the built-in table (measured per
+ * precision and order by the package's autotune module).  Process-wide: set it only while no
+ * solve is running.  Returns 0, or -1 for any other nbt (the setting is then unchanged). */
+int feast_tune_sweep_block(int nbt);
+
 /* Parallel-order two-sided Jacobi eigendecomposition of a Hermitian m x m matrix H
  * (ld m, complex128, not modified): the reduced eigenproblem of the Appendix, step 2.i.
  * d: device m doubles (eigenvalues ascending); W: device m x m eigenvectors (ld m).

@@ -113,8 +113,17 @@ def lib():
                                       cl, _vp]
         L.feast_kern_lu.argtypes = [ci, _vp, ci, ci, ci, _dp, _vp, _ip, _ip, _vp]
         L.feast_kern_jacobi.argtypes = [_vp, ci, _vp, _vp, _vp]
+        L.feast_tune_sweep_block.argtypes = [ci]
         _lib = L
     return _lib
+
+
+def tune_sweep_block(nbt):
+    """Process-wide sweep block height for later factorizations (64, 128, 256 or 512; 0: the
+    built-in tuned table).  Set it only while no solve is running."""
+    st = lib().feast_tune_sweep_block(int(nbt))
+    if st != 0:
+        raise ValueError(f"sweep block height must be 0, 64, 128, 256 or 512, not {nbt}")
 
 
 def fortran(t):

@@ -320,7 +320,7 @@ int ensure_factors(feast_ctx* h, int dt, int n, const void* A, int lda, double e
     return 0;
   h->f_valid = false;
   hipStream_t s = h->stream;
-  const int nbt = sweep_block(n);
+  const int nbt = sweep_block(n, prec == FEAST_FP64 ? 0 : 1);
   const int np = (n + nbt - 1) / nbt * nbt;
   // nodes and weights
   h->z.resize(nc);

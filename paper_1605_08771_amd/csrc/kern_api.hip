@@ -8,8 +8,8 @@
 using namespace feast;
 
 namespace {
-int pick_np(int n) {  // the padding the solver uses (a multiple of the sweep block height)
-  const int nbt = sweep_block(n);
+int pick_np(int n, int prec) {  // the padding the solver uses (a multiple of the sweep block)
+  const int nbt = sweep_block(n, prec == 0 ? 0 : 1);
   return (n + nbt - 1) / nbt * nbt;
 }
 }  // namespace
@@ -59,7 +59,7 @@ extern "C" int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, co
   if (lda < n) return -3;
   if (nc < 1) return -5;
   if (!z) return -6;
-  const int np = pick_np(n);
+  const int np = pick_np(n, prec);
   if (np_out) *np_out = np;
   if (!LU) return 0;
   if (!perm) return -8;
@@ -92,6 +92,8 @@ extern "C" int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, co
     return -101;
   }
 }
+
+extern "C" int feast_tune_sweep_block(int nbt) { return set_sweep_block_override(nbt); }
 
 extern "C" int feast_kern_jacobi(const void* H, int m, double* d, void* W, void* hip_stream) {
   if (!H) return -1;

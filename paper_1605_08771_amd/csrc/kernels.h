@@ -123,9 +123,12 @@ void gather_rhs(hipStream_t s, const zd* X, long ldx, int n, int np, int m0, int
 void gather_rhs_f32(hipStream_t s, const zd* X, long ldx, int n, int np, int m0, int nc,
                     int sides, const int* perm, zf* B);
 
-// Height of the sweep blocks (and of the inverted diagonal blocks) for order n: the factors
-// are padded to a multiple of it.
-int sweep_block(int n);
+// Height of the sweep blocks (and of the inverted diagonal blocks) for order n and the
+// factors' precision class (0: FP64, 1: FP32 factors): the factors are padded to a multiple
+// of it.  set_sweep_block_override(nbt) makes every later call return nbt (64, 128, 256 or
+// 512; 0 restores the table), for tuning runs; returns -1 on any other value.
+int sweep_block(int n, int prec_class);
+int set_sweep_block_override(int nbt);
 // Forward then backward block sweeps for all (node, side) systems.  B (input RHS, destroyed)
 // and Y (output) are [nc][sides] blocks of np x m0.
 void solve_sweeps_f64(hipStream_t s, const zd* LU, const zd* invL, const zd* invU, int np,

@@ -106,7 +106,7 @@ extern "C" int feast_filter_apply_noalloc(feast_dtype dt, int n, const void* A, 
   if (!Q || Q == X) return -11;
   if (ldq < n) return -12;
   const int sides = (dt == FEAST_C128) ? 2 : 1;
-  const int nbt = sweep_block(n);
+  const int nbt = sweep_block(n, 0);
   const int np = (n + nbt - 1) / nbt * nbt;
   // Layout (and size check) before any device work.
   Carve cv{0};

@@ -11,8 +11,11 @@
 // inverses (computed once per factorization), the off-diagonal blocks through one GEMM per
 // block step, so every flop of the sweep runs on the matrix cores.  U^H and L^H are never
 // formed: the GEMM reads U and L with a conjugate-transpose operand.
+#include <atomic>
+
 #include "common.h"
 #include "kernels.h"
+#include "sweep_tune.h"
 
 namespace feast {
 
@@ -320,11 +323,32 @@ void gather_rhs_f32(hipStream_t s, const zd* X, long ldx, int n, int np, int m0,
   FEAST_LAUNCH_CHECK();
 }
 
-int sweep_block(int n) {
-  if (n >= 8192) return 512;
-  if (n >= 2048) return 256;
-  if (n >= 384) return 128;
-  return 64;
+namespace {
+std::atomic<int> g_sweep_override{0};
+}
+
+// The tuned table (sweep_tune.h, written by the package's autotune module from measured
+// solves), unless the process-wide override is set.  Rows are ordered by n_max within a
+// precision class; orders beyond the last row take the largest height the FP64 residual
+// floor allows.  A row holds for a range of orders measured at one of them, so the height is
+// halved (down to 64) while padding n to a multiple of it would add more than n / 8 rows.
+int sweep_block(int n, int prec_class) {
+  const int o = g_sweep_override.load(std::memory_order_relaxed);
+  if (o > 0) return o;
+  int nbt = 512;
+  for (const SweepTuneRow& r : kSweepTune)
+    if (r.prec_class == prec_class && n <= r.n_max) {
+      nbt = r.nbt;
+      break;
+    }
+  while (nbt > 64 && 8L * ((n + nbt - 1) / nbt * nbt - n) > n) nbt /= 2;
+  return nbt;
+}
+
+int set_sweep_block_override(int nbt) {
+  if (nbt != 0 && nbt != 64 && nbt != 128 && nbt != 256 && nbt != 512) return -1;
+  g_sweep_override.store(nbt, std::memory_order_relaxed);
+  return 0;
 }
 
 void solve_sweeps_f64(hipStream_t s, const zd* LU, const zd* invL, const zd* invU, int np,

@@ -162,6 +162,32 @@ def test_kernel_api_argument_checks():
     assert L.feast_kern_jacobi(None, 4, None, None, None) == -1
 
 
+def test_sweep_block_override():
+    """The tuning hook: heights 64..512 change the padding the factorizations use; 0 restores
+    the table; anything else is rejected and leaves the setting alone."""
+    L = fm.lib()
+    npo = ctypes.c_int()
+    zp = ctypes.cast((ctypes.c_double * 2)(0.0, 1.0), ctypes.POINTER(ctypes.c_double))
+
+    def np_for(n, prec=0):
+        assert L.feast_kern_lu(prec, DEV, n, n, 1, zp, None, None, ctypes.byref(npo), None) == 0
+        return npo.value
+    try:
+        base = np_for(300)
+        assert base % 64 == 0 and 300 <= base <= 300 + 300 // 8  # padding rule of the table
+        fm.tune_sweep_block(512)
+        assert np_for(300) == 512 and np_for(300, 1) == 512
+        assert L.feast_tune_sweep_block(100) == -1
+        assert np_for(300) == 512
+        fm.tune_sweep_block(64)
+        assert np_for(300) == 320 and np_for(1000, 1) == 1024
+        with pytest.raises(ValueError):
+            fm.tune_sweep_block(1024)
+    finally:
+        fm.tune_sweep_block(0)
+    assert np_for(300) == base
+
+
 def test_binding_rejects_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(fm, "_lib", None)
     monkeypatch.setattr(fm, "LIB_PATH", str(tmp_path / "missing.so"))

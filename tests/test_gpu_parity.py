@@ -54,6 +54,33 @@ def test_filter_apply_vs_oracle(fe, orc, dtype, n, m0):
     assert err < 1e-11, err
 
 
+@pytest.mark.parametrize("nbt", [64, 128, 256, 512])
+def test_filter_apply_vs_oracle_each_sweep_block(fe, orc, nbt):
+    """Every sweep block height the tuned table may pick, forced through the tuning hook:
+    the FP64 filter at n = 600 (ragged: the padded rows differ per height) against the oracle,
+    and the FP32-factor filter with its FP64 refinement against the same reference."""
+    import torch
+    import paper_1605_08771_amd as fm
+    n, m0 = 600, 31
+    rng = gen.rng_for([37, n])
+    emin, emax = -0.1, 0.1
+    lam = gen.uniform_spectrum(rng, n, emin, emax)
+    p = gen.make_problem(lam, emin, emax, m0, 8, 1e-12, 10, True, rng)
+    ref = orc.filter_apply("c128", p.A, emin, emax, 8, p.X0)
+    fm.tune_sweep_block(nbt)
+    try:
+        for prec, tol in ((fm.FEAST_FP64, 1e-11), (fm.FEAST_FP32_IR, 1e-9)):
+            fe.invalidate()
+            st, Q = fe.filter_apply(_dev(p.A), _dev(p.X0), emin, emax, 8, prec=prec)
+            torch.cuda.synchronize()
+            assert st == 0
+            err = np.abs(Q.cpu().numpy() - ref).max() / np.abs(ref).max()
+            assert err < tol, (nbt, prec, err)
+    finally:
+        fm.tune_sweep_block(0)
+        fe.invalidate()
+
+
 def test_filter_apply_diagonal_nodes(fe):
     """A = diag(lam): Q_ik = rho(lam_i) X_ik with the closed-form rho (nodes and weights)."""
     import torch
