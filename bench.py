@@ -44,18 +44,21 @@ PRECS = {"fp64": 0, "fp32ir": 1, "bf16x3ir": 2}
 DEFAULT_PREC = {"c1": "fp64", "c2": "fp64", "c3": "fp32ir", "c4": "fp32ir", "c5": "fp32ir"}
 
 # HBM bytes per launch of the paired sweep GEMM, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs
-# scaled by a plain copy of known size, keyed by (workload, precision); valid only while the
-# sources of that kernel (gemm.hip), of its launches and block height (solve.hip) and their
-# common header hash to the version the counters were taken on.
+# over the solver's sweep launches at the workload's order, block and node count (the sweeps
+# microbenchmark) scaled by a plain copy of known size, keyed by (workload, precision); valid
+# only while the sources of that kernel (gemm.hip), of its launches (solve.hip), of the block
+# height table (sweep_tune.h) and their common header hash to the version the counters were
+# taken on.
 SWEEP_TRAFFIC = {
-    ("c2", "fp64"): {"sources": "c50978dcbb339c8e", "bytes_per_launch": 9.554e8},
+    ("c2", "fp64"): {"sources": "e4628a063658a6a8", "bytes_per_launch": 9.530e8},
+    ("c5", "fp32ir"): {"sources": "e4628a063658a6a8", "bytes_per_launch": 3.623e9},
 }
 
 
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("gemm.hip", "solve.hip", "common.h"):
+    for f in ("gemm.hip", "solve.hip", "sweep_tune.h", "common.h"):
         with open(os.path.join(ROOT, "paper_1605_08771_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

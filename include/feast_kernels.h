@@ -39,6 +39,20 @@ int feast_kern_gemm(int prec, int opA, int opB, int M, int N, int K, const doubl
 int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, const double* z, void* LU,
                   int* perm, int* np_out, void* hip_stream);
 
+/* The block triangular sweeps of the Sec. 1 linear solves on given factors (the solver's own
+ * launches, for tests and counter runs).  LU: nc blocks of np x np (ld np; complex128 for
+ * prec 0, complex64 for prec 1 and 2, as feast_kern_lu writes them: unit-lower L and U of
+ * P M_j).  invL, invU: nc blocks of np x nbt receiving (compute_inverses != 0) or holding the
+ * inverses of the nbt x nbt diagonal blocks of L and U.  B: nc blocks of sides x np x m0
+ * (ld np): on entry the right-hand sides, on exit side 0 holds (L U)^{-1} B_0 and side 1
+ * (L U)^{-H} B_1 (both adjoint systems of the quadrature share the factors); Z: scratch of
+ * B's size.  With LU NULL only np and nbt are returned (*np_out, *nbt_out).  Synchronises the
+ * stream.  Returns 0, -1..-7 for an invalid argument (prec, n, nc, m0, sides, invL/invU,
+ * B/Z), -101 on a HIP error. */
+int feast_kern_sweeps(int prec, int n, int nc, int m0, int sides, const void* LU, void* invL,
+                      void* invU, int compute_inverses, void* B, void* Z, int* np_out,
+                      int* nbt_out, void* hip_stream);
+
 /* Tuning hook for the block triangular sweeps of the Sec. 1 linear solves: every later
  * factorization (and its solves) uses sweep blocks of nbt rows (64, 128, 256 or 512) and pads
  * the factors to a multiple of nbt; nbt = 0 restores the built-in table (measured per

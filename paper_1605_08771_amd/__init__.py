@@ -114,6 +114,8 @@ def lib():
         L.feast_kern_lu.argtypes = [ci, _vp, ci, ci, ci, _dp, _vp, _ip, _ip, _vp]
         L.feast_kern_jacobi.argtypes = [_vp, ci, _vp, _vp, _vp]
         L.feast_tune_sweep_block.argtypes = [ci]
+        L.feast_kern_sweeps.argtypes = [ci, ci, ci, ci, ci, _vp, _vp, _vp, ci, _vp, _vp, _ip,
+                                        _ip, _vp]
         _lib = L
     return _lib
 
@@ -488,6 +490,43 @@ class Feast:
                                  None, _vp(self._stream.cuda_stream))
         # blocks are column-major: element (r, c) of node j at LU[j].flatten()[r + c*np]
         return st, LU.transpose(1, 2), perm
+
+    def sweep_shape(self, n, prec=0):
+        """(np, nbt): the padded order and sweep block height the solver uses for order n."""
+        npo, nbo = ctypes.c_int(), ctypes.c_int()
+        st = lib().feast_kern_sweeps(prec, n, 1, 1, 1, None, None, None, 0, None, None,
+                                     ctypes.byref(npo), ctypes.byref(nbo), None)
+        if st != 0:
+            raise ValueError(f"feast_kern_sweeps returned {st}")
+        return npo.value, nbo.value
+
+    def sweeps(self, LU, B, n, sides, invL=None, invU=None, prec=0):
+        """The solver's block sweeps on factors LU [nc, np, np] (as lu() returns them) for
+        right-hand sides B [nc, sides, m0, np] (each block column-major, modified in place:
+        side 0 -> (L U)^{-1} B_0, side 1 -> (L U)^{-H} B_1).  The diagonal-block inverses are
+        computed here unless invL and invU [nc, nbt, np] are given.  Returns the status."""
+        import torch
+        nc = LU.shape[0]
+        np_, nbt = self.sweep_shape(n, prec)
+        m0 = B.shape[2]
+        dt = torch.complex128 if prec == 0 else torch.complex64
+        if tuple(LU.shape) != (nc, np_, np_) or LU.dtype != dt:
+            raise ValueError("LU must be [nc, np, np] of the precision's dtype")
+        if tuple(B.shape) != (nc, sides, m0, np_) or B.dtype != dt or not B.is_contiguous():
+            raise ValueError("B must be a contiguous [nc, sides, m0, np] tensor")
+        comp = invL is None
+        if comp:
+            invL = torch.empty((nc, nbt, np_), dtype=dt, device=LU.device)
+            invU = torch.empty_like(invL)
+        Z = torch.empty_like(B)
+        # lu() hands back column-major blocks as transposed views of contiguous storage
+        base = LU.transpose(1, 2)
+        if not base.is_contiguous():
+            raise ValueError("LU must be the column-major blocks lu() returns")
+        return lib().feast_kern_sweeps(prec, n, nc, m0, sides, _vp(base.data_ptr()),
+                                       _vp(invL.data_ptr()), _vp(invU.data_ptr()), int(comp),
+                                       _vp(B.data_ptr()), _vp(Z.data_ptr()), None, None,
+                                       _vp(self._stream.cuda_stream))
 
     def jacobi(self, H):
         import torch

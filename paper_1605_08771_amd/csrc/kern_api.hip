@@ -93,6 +93,47 @@ extern "C" int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, co
   }
 }
 
+extern "C" int feast_kern_sweeps(int prec, int n, int nc, int m0, int sides, const void* LU,
+                                 void* invL, void* invU, int compute_inverses, void* B, void* Z,
+                                 int* np_out, int* nbt_out, void* hip_stream) {
+  if (prec < 0 || prec > 2) return -1;
+  if (n < 1) return -2;
+  if (nc < 1) return -3;
+  if (m0 < 1) return -4;
+  if (sides != 1 && sides != 2) return -5;
+  const int cls = prec == 0 ? 0 : 1;
+  const int nbt = sweep_block(n, cls);
+  const int np = (n + nbt - 1) / nbt * nbt;
+  if (np_out) *np_out = np;
+  if (nbt_out) *nbt_out = nbt;
+  if (!LU) return 0;
+  if (!invL || !invU) return -6;
+  if (!B || !Z || B == Z) return -7;
+  try {
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t esz = prec == 0 ? sizeof(zd) : sizeof(zf);
+    void* tmp = nullptr;
+    if (compute_inverses) FEAST_HIP(hipMalloc(&tmp, esz * (size_t)np * nbt));
+    if (prec == 0) {
+      if (compute_inverses)
+        tri_inverse_blocks_f64(s, (const zd*)LU, np, nc, nbt, (zd*)invL, (zd*)invU, (zd*)tmp);
+      solve_sweeps_f64(s, (const zd*)LU, (const zd*)invL, (const zd*)invU, np, nc, nbt, sides, m0,
+                       (zd*)B, (zd*)Z);
+    } else {
+      SplitBf16Scope split(prec == 2);
+      if (compute_inverses)
+        tri_inverse_blocks_f32(s, (const zf*)LU, np, nc, nbt, (zf*)invL, (zf*)invU, (zf*)tmp);
+      solve_sweeps_f32(s, (const zf*)LU, (const zf*)invL, (const zf*)invU, np, nc, nbt, sides, m0,
+                       (zf*)B, (zf*)Z);
+    }
+    FEAST_HIP(hipStreamSynchronize(s));
+    if (tmp) FEAST_HIP(hipFree(tmp));
+    return 0;
+  } catch (const HipError&) {
+    return -101;
+  }
+}
+
 extern "C" int feast_tune_sweep_block(int nbt) { return set_sweep_block_override(nbt); }
 
 extern "C" int feast_kern_jacobi(const void* H, int m, double* d, void* W, void* hip_stream) {

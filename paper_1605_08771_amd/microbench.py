@@ -3,6 +3,7 @@
     python -m paper_1605_08771_amd.microbench gemm --prec fp64 --shape 61440 300 512 --reps 4
     python -m paper_1605_08771_amd.microbench jacobi --m 300 --kind random --reps 3
     python -m paper_1605_08771_amd.microbench filter --n 32768 --m0 768 --prec fp32ir
+    python -m paper_1605_08771_amd.microbench sweeps --n 32768 --m0 768 --prec fp32
 
 `gemm` runs C = -op(A) op(B) + C through `feast_kern_gemm` (prec fp64, fp64x3 (three real
 FP64 products per complex one), fp32 or bf16x3) on
@@ -122,6 +123,47 @@ def _filter(a):
     f.close()
 
 
+def _sweeps(a):
+    """The solver's block sweeps (both adjoint sides, all nodes) at order n with an m0-column
+    block, on placeholder factors (identity diagonal, small off-diagonal entries): the launch
+    shapes of one filter application's solves without the factorization before them."""
+    import torch
+    import paper_1605_08771_amd as fm
+    prec = {"fp64": 0, "fp32": 1, "bf16x3": 2}[a.prec]
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    f = fm.Feast()
+    np_, nbt = f.sweep_shape(a.n, prec)
+    base = torch.full((a.nc, np_, np_), 1e-4, dtype=dt, device="cuda")
+    base.diagonal(dim1=1, dim2=2).fill_(1.0)
+    LU = base.transpose(1, 2)
+    invL = torch.empty((a.nc, nbt, np_), dtype=dt, device="cuda")
+    invU = torch.empty_like(invL)
+    B = torch.ones((a.nc, 2, a.m0, np_), dtype=dt, device="cuda")
+    st = f.sweeps(LU, B, a.n, 2, prec=prec)  # computes the inverse blocks (untimed)
+    if st != 0:
+        raise SystemExit(f"feast_kern_sweeps returned {st}")
+    lib = fm.lib()
+    Z = torch.empty_like(B)
+    times = []
+    for _ in range(a.reps):
+        B.fill_(1.0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(f._stream)
+        st = lib.feast_kern_sweeps(prec, a.n, a.nc, a.m0, 2, fm._vp(base.data_ptr()),
+                                   fm._vp(invL.data_ptr()), fm._vp(invU.data_ptr()), 0,
+                                   fm._vp(B.data_ptr()), fm._vp(Z.data_ptr()), None, None,
+                                   fm._vp(f._stream.cuda_stream))
+        e1.record(f._stream)
+        e1.synchronize()
+        if st != 0:
+            raise SystemExit(f"feast_kern_sweeps returned {st}")
+        times.append(e0.elapsed_time(e1))
+    print(f"sweeps n={a.n} np={np_} nbt={nbt} m0={a.m0} n_c={a.nc} {a.prec}: "
+          f"{min(times):.3f} ms per filter application's sweeps (min of {a.reps})", flush=True)
+    f.close()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -141,6 +183,12 @@ def main(argv=None):
     j.add_argument("--kind", choices=["random", "gram"], default="random")
     j.add_argument("--reps", type=int, default=3)
     j.add_argument("--seed", type=int, default=0)
+    sw = sub.add_parser("sweeps")
+    sw.add_argument("--n", type=int, required=True)
+    sw.add_argument("--m0", type=int, required=True)
+    sw.add_argument("--nc", type=int, default=8)
+    sw.add_argument("--prec", choices=["fp64", "fp32", "bf16x3"], default="fp32")
+    sw.add_argument("--reps", type=int, default=2)
     fl = sub.add_parser("filter")
     fl.add_argument("--n", type=int, required=True)
     fl.add_argument("--m0", type=int, required=True)
@@ -148,7 +196,7 @@ def main(argv=None):
     fl.add_argument("--prec", choices=["fp64", "fp32ir", "bf16x3ir"], default="fp32ir")
     fl.add_argument("--seed", type=int, default=0)
     a = ap.parse_args(argv)
-    {"gemm": _gemm, "jacobi": _jacobi, "filter": _filter}[a.what](a)
+    {"gemm": _gemm, "jacobi": _jacobi, "filter": _filter, "sweeps": _sweeps}[a.what](a)
 
 
 if __name__ == "__main__":

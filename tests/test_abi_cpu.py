@@ -162,6 +162,26 @@ def test_kernel_api_argument_checks():
     assert L.feast_kern_jacobi(None, 4, None, None, None) == -1
 
 
+def test_kern_sweeps_argument_checks_and_shape_query():
+    L = fm.lib()
+    npo, nbo = ctypes.c_int(), ctypes.c_int()
+
+    def q(prec=0, n=300, nc=1, m0=4, sides=2):
+        return L.feast_kern_sweeps(prec, n, nc, m0, sides, None, None, None, 0, None, None,
+                                   ctypes.byref(npo), ctypes.byref(nbo), None)
+    assert q(prec=3) == -1 and q(n=0) == -2 and q(nc=0) == -3 and q(m0=0) == -4
+    assert q(sides=3) == -5
+    for n in (1, 63, 300, 1000, 2100, 5000, 8192, 20000):
+        for prec in (0, 1):
+            assert q(prec=prec, n=n) == 0
+            assert npo.value % nbo.value == 0 and npo.value >= n
+            assert nbo.value == 64 or 8 * (npo.value - n) <= n
+    assert L.feast_kern_sweeps(0, 300, 1, 4, 2, DEV, None, DEV, 0, DEV, DEV, None, None,
+                               None) == -6
+    assert L.feast_kern_sweeps(0, 300, 1, 4, 2, DEV, DEV, DEV, 0, DEV, DEV, None, None,
+                               None) == -7
+
+
 def test_sweep_block_override():
     """The tuning hook: heights 64..512 change the padding the factorizations use; 0 restores
     the table; anything else is rejected and leaves the setting alone."""

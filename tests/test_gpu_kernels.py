@@ -210,6 +210,41 @@ def test_short_panel_groups_match_column_steps(fe, n, prec):
     assert torch.equal(torch.view_as_real(LU1.contiguous()), torch.view_as_real(LU2.contiguous()))
 
 
+@pytest.mark.parametrize("n,prec,sides", [(300, 0, 2), (700, 1, 2), (1100, 0, 1), (1500, 1, 2),
+                                          (2100, 0, 2)])
+def test_kern_sweeps_solve_both_adjoint_systems(fe, n, prec, sides):
+    """The solver's block sweeps on feast_kern_lu's factors: side 0 solves (L U) y = b and side
+    1 solves (L U)^H y = b, each to a backward error of a few units of the factors' precision."""
+    import torch
+    rng = np.random.default_rng(n + 11 * prec)
+    G = _crand(rng, n, n)
+    A = 0.5 * (G + G.conj().T) / np.sqrt(n)
+    z = np.array([0.1 + 0.05j, -0.3 + 0.02j])
+    st, LU, perm = fe.lu(_dev(A), z, prec=prec)
+    assert st == 0
+    np_, nbt = fe.sweep_shape(n, prec)
+    assert LU.shape[1] == np_
+    m0 = 23
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    B0 = rng.standard_normal((2, sides, m0, np_)) + 1j * rng.standard_normal((2, sides, m0, np_))
+    B = torch.from_numpy(B0).to(dt).cuda().contiguous()
+    assert fe.sweeps(LU, B, n, sides, prec=prec) == 0
+    torch.cuda.synchronize()
+    Y = B.cpu().numpy().astype(np.complex128)
+    LUh = LU.cpu().numpy().astype(np.complex128)
+    eps = np.finfo(np.float64 if prec == 0 else np.float32).eps
+    for j in range(2):
+        L = np.tril(LUh[j], -1) + np.eye(np_)
+        U = np.triu(LUh[j])
+        for sd in range(sides):
+            Mj = L @ U if sd == 0 else (L @ U).conj().T
+            rhs = B0[j, sd].T.astype(np.complex128 if prec == 0 else np.complex64)
+            rhs = rhs.astype(np.complex128)
+            y = Y[j, sd].T
+            be = np.linalg.norm(Mj @ y - rhs) / (np.linalg.norm(Mj) * np.linalg.norm(y) * np_ * eps)
+            assert be < 5.0, (j, sd, be)
+
+
 @pytest.mark.parametrize("m", [1, 2, 7, 31, 33, 64, 75, 301, 512, 513, 900])
 def test_jacobi_vs_lapack(fe, m):
     import torch
