@@ -245,6 +245,31 @@ def test_kern_sweeps_solve_both_adjoint_systems(fe, n, prec, sides):
             assert be < 5.0, (j, sd, be)
 
 
+@pytest.mark.parametrize("m,k", [(300, 40), (700, 150), (96, 20), (513, 9)])
+def test_jacobi_deflation_structured(fe, m, k):
+    """A reduced matrix of the kind FEAST produces once most Ritz pairs have converged: a
+    diagonal part with couplings below the convergence floor and a dense coupled block on k
+    scattered indices.  After the first sweep only those columns stay active, so the sweeps
+    continue on the compacted block (deflation); eigenvalues and eigenvectors still match."""
+    import torch
+    rng = np.random.default_rng(1000 + m + k)
+    H = np.diag(rng.uniform(-1.0, 1.0, m)).astype(complex)
+    E = 1e-18 * (rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)))
+    H += 0.5 * (E + E.conj().T)
+    S = np.sort(rng.choice(m, size=k, replace=False))
+    G = _crand(rng, k, k)
+    H[np.ix_(S, S)] += 0.25 * (G + G.conj().T)
+    sweeps, d, W = fe.jacobi(torch.from_numpy(H).cuda())
+    torch.cuda.synchronize()
+    assert sweeps >= 0
+    d = d.cpu().numpy()
+    W = W.cpu().numpy()
+    tol = max(1e-13, 4 * m * np.finfo(float).eps) * np.linalg.norm(H, 2)
+    np.testing.assert_allclose(d, np.linalg.eigvalsh(H), rtol=0, atol=tol)
+    np.testing.assert_allclose(W.conj().T @ W, np.eye(m), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(H @ W, W * d, rtol=0, atol=1e-12 * np.linalg.norm(H, 2))
+
+
 @pytest.mark.parametrize("m", [1, 2, 7, 31, 33, 64, 75, 301, 512, 513, 900])
 def test_jacobi_vs_lapack(fe, m):
     import torch
