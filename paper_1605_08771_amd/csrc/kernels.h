@@ -200,10 +200,16 @@ typedef std::map<int, JacobiGraph> JacobiGraphs;
 int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* dflag,
                 int max_sweeps, JacobiGraphs* caches, int mp);
 inline int jacobi_order(int m) { return (m + 31) / 32 * 32; }
+// Deflation starts once the active columns (rounded up to 32) are at most
+// kJacobiDeflNum / kJacobiDeflDen of the current order (measured against 3/4 and 7/8 on
+// config 2: within 3 % of each other).
+constexpr int kJacobiDeflNum = 1, kJacobiDeflDen = 2;
+// Largest compacted order at padded order mp.
+inline size_t jacobi_defl_max(int mp) { return (size_t)mp * kJacobiDeflNum / kJacobiDeflDen; }
 // Complex entries of jacobi_eigh's work array at padded order mp.
 inline size_t jacobi_work(int mp) {
   return (size_t)mp * mp + 32 * (size_t)mp + 40 + (5 * (size_t)mp + 3) / 4 +
-         2 * (size_t)(mp / 2) * (mp / 2);
+         2 * jacobi_defl_max(mp) * jacobi_defl_max(mp);
 }
 // Padded order used by callers that record sweeps for several nearby sizes.
 inline int jacobi_order_quantized(int m) { return jacobi_order(m); }

@@ -107,12 +107,18 @@ __global__ __launch_bounds__(256) void chol_rowpanel_kernel(const zd* R, int ld,
   }
 }
 
-// Inverse of the b x b (b <= 64) upper block at R into out (identity-padded in LDS).
-__global__ __launch_bounds__(256) void upper_inv_small_kernel(const zd* R, int ldr, int b, zd* out,
+// Inverses of the diagonal blocks of the m x m upper R, one workgroup per block: block j
+// (b = min(64, m - 64 j) rows from row 64 j) into the same position of out (identity-padded
+// in LDS).
+__global__ __launch_bounds__(256) void upper_inv_small_kernel(const zd* R, int ldr, int m, zd* out,
                                                               int ldo) {
   __shared__ zd Tm[CB][CB + 1];
   __shared__ zd X[CB][CB + 1];
   const int t = threadIdx.x;
+  const int j0 = blockIdx.x * CB;
+  const int b = (m - j0 < CB) ? m - j0 : CB;
+  R += j0 + (long)j0 * ldr;
+  out += j0 + (long)j0 * ldo;
   for (int e = t; e < CB * CB; e += 256) {
     int r = e % CB, c = e / CB;
     Tm[r][c] = (r < b && c < b) ? R[r + (long)c * ldr] : zmake(r == c ? 1 : 0, 0);
@@ -628,13 +634,13 @@ void cholesky_upper(hipStream_t s, zd* G, int m, int ldg, int* flag, zd* tmp) {
 }
 
 void upper_inverse(hipStream_t s, const zd* R, int m, int ldr, zd* Rinv, int ldi, zd* tmp) {
-  // Rinv must be zero on entry.  Block columns of 64: Rinv_jj = R_jj^{-1};
-  // Rinv[0:j, j] = -Rinv[0:j, 0:j] (R[0:j, j] Rinv_jj).
+  // Rinv must be zero on entry.  Block columns of 64: Rinv_jj = R_jj^{-1} (all diagonal
+  // blocks in one launch); Rinv[0:j, j] = -Rinv[0:j, 0:j] (R[0:j, j] Rinv_jj).
+  hipLaunchKernelGGL(upper_inv_small_kernel, dim3((m + CB - 1) / CB), dim3(256), 0, s, R, ldr, m,
+                     Rinv, ldi);
+  FEAST_LAUNCH_CHECK();
   for (int j = 0; j < m; j += CB) {
     int b = (m - j < CB) ? m - j : CB;
-    hipLaunchKernelGGL(upper_inv_small_kernel, dim3(1), dim3(256), 0, s, R + j + (long)j * ldr, ldr,
-                       b, Rinv + j + (long)j * ldi, ldi);
-    FEAST_LAUNCH_CHECK();
     if (j > 0) {
       zgemm(s, OP_N, OP_N, j, b, b, zmake(1, 0), R + (long)j * ldr, ldr, Rinv + j + (long)j * ldi,
             ldi, zmake(0, 0), tmp, j);
@@ -692,7 +698,7 @@ JacobiLayout jacobi_layout(zd* work, int mp) {
   L.cmap[0] = ints + 3 * mp;
   L.cmap[1] = ints + 4 * mp;
   zd* hc = L.Ubuf + (long)mp * JP + 40 + (5L * mp + 3) / 4;
-  const long half = (long)(mp / 2) * (mp / 2);
+  const long half = (long)jacobi_defl_max(mp) * (long)jacobi_defl_max(mp);
   L.Hc[0] = hc;
   L.Hc[1] = hc + half;
   return L;
@@ -774,7 +780,7 @@ int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* df
     int count = 0;
     for (int i = 0; i < mc; ++i) count += flags[i] != 0;
     const int mn = (count + JP - 1) / JP * JP;
-    if (mn > mc / 2) continue;
+    if ((long)mn * kJacobiDeflDen > (long)mc * kJacobiDeflNum) continue;
     // active columns first, then converged ones up to a multiple of 32
     sel.clear();
     keep.assign(mc, 0);
