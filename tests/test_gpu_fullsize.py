@@ -116,6 +116,38 @@ def test_c2_solve_full_size(fe, c2, prec, method, expand, tol):
     _check_converged(c2, out, tol, target=1e-8 if tol <= 1e-12 else None)
 
 
+def _golden(name):
+    import os
+    vals = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                k, v = (x.strip() for x in line.split("="))
+                vals[k] = float(v)
+    return vals
+
+
+def test_c2_trace_vs_oracle_fixture(fe, c2):
+    """Config 2 at full size against the FP64 CPU oracle: the largest counted residual after
+    each of the first iterations of FEAST (FP64, filter-value test on), against the oracle's
+    trace on the same seeded input (tests/golden/c2_oracle_trace.txt, written by
+    make_c2_oracle_trace.py from the oracle alone).  The two sides orthonormalize differently
+    (Cholesky-QR against the Gram route) and round differently, so the traces agree to a
+    relative 1e-3 while the residual is far above the rounding floor."""
+    import torch
+    g = _golden("c2_oracle_trace.txt")
+    its = int(g["iterations"])
+    ref = np.array([g[f"trace_{i + 1}"] for i in range(its)])
+    fe.invalidate()
+    out = fe.solve(c2.A, c2.emin, c2.emax, c2.m0, n_c=c2.n_c, tol=1e-30, max_iter=its,
+                   anorm=c2.anorm, X0=c2.X0, prec=0, spurious=True, refine_max=0)
+    torch.cuda.synchronize()
+    fe.invalidate()
+    assert out["status"] == 1 and out["iters"] == its
+    np.testing.assert_allclose(out["trace"], ref, rtol=1e-3, atol=0)
+
+
 def test_c3_mixed_solve_full_size(fe):
     """Config 3 (n = 16384, m0 = 400, n_c = 16) with FP32 factors and FP64 refinement, to the
     configuration's own tolerance 1e-12."""
