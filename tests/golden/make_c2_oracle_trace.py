@@ -2,7 +2,7 @@
 (complex Hermitian n = 8192, 200 eigenvalues in I = (-0.05, 0.05) with edge clusters inside
 and outside, m0 = 300, n_c = 8; the filter-value test on), for the first iterations of the
 FEAST algorithm of the Appendix.  It calls only the oracle and the input generator; the GPU
-path never contributes to the file.  Takes about an hour and a half on 8 cores.
+path never contributes to the file.  Takes about three and a half hours on 8 cores.
 
     python tests/golden/make_c2_oracle_trace.py [iterations]
 """
