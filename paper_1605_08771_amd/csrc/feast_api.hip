@@ -295,7 +295,7 @@ struct feast_ctx {
   double last_max_res = 0;
   PhaseTimer timer;
   KernelProfiler prof;
-  JacobiGraphs jgraphs;  // recorded Jacobi sweeps, by order and buffer
+  std::map<int, JacobiGraph> jgraphs;  // recorded Jacobi sweeps, by padded order
   // expanded-subspace variants
   Buf b_win, b_U, b_Rsel, b_lsel, b_keep, b_sel, b_T;
   std::vector<int> keep_h, sel_h;
@@ -690,7 +690,7 @@ int rr_core(feast_ctx* h, const zd* A, long lda, int n, zd* Qin, long ldq, int m
   int* dflag = h->b_flag.get<int>(64);
   hipEvent_t ej = h->prof.on ? h->prof.pool.take() : nullptr;
   if (ej) FEAST_HIP(hipEventRecord(ej, s));
-  int sweeps = jacobi_eigh(s, H, m0, d, V, jw, dflag, kJacobiMaxSweeps, &h->jgraphs, mp);
+  int sweeps = jacobi_eigh(s, H, m0, d, V, jw, dflag, kJacobiMaxSweeps, &h->jgraphs[mp], mp);
   if (ej) h->prof.eig(s, ej, sweeps);
   if (sweeps < 0) return FEAST_EIG_FAILED;
   double* lam = h->b_lam.get<double>(mp);
@@ -796,7 +796,7 @@ int gram_orthonormal(feast_ctx* h, int n, int k, zd* B, zd* U) {
   int* dflag = h->b_flag.get<int>(64);
   hipEvent_t ej = h->prof.on ? h->prof.pool.take() : nullptr;
   if (ej) FEAST_HIP(hipEventRecord(ej, s));
-  int sweeps = jacobi_eigh(s, G, k, d, V, jw, dflag, kJacobiMaxSweeps, &h->jgraphs, mp);
+  int sweeps = jacobi_eigh(s, G, k, d, V, jw, dflag, kJacobiMaxSweeps, &h->jgraphs[mp], mp);
   if (ej) h->prof.eig(s, ej, sweeps);
   if (sweeps < 0) return -2;
   std::vector<double> hd(k);

@@ -1,8 +1,6 @@
 // Internal launchers of the FEAST MI355X library.  All device pointers; every launch is
 // asynchronous on the given stream.
 #pragma once
-#include <map>
-#include <vector>
 #include "common.h"
 
 namespace feast {
@@ -172,45 +170,29 @@ void upper_inverse(hipStream_t s, const zd* R, int m, int ldr, zd* Rinv, int ldi
 // A rotation is skipped when |h_pq| <= max(1e-17 sqrt(|h_pp h_qq|), eps ||H||_F); a sweep
 // ends the iteration when no off-diagonal entry exceeds max(1e-17 sqrt(|h_pp h_qq|), 4 eps ||H||_F).
 // Returns sweeps used (host sync per sweep) or -1.  d (device, mp) eigenvalues unsorted,
-// V (device, mp x mp, ld mp) eigenvectors; work: jacobi_work(mp) complex.  Once at most half
-// of the current order's columns (rounded up to 32) still have an off-diagonal entry above the
-// floor, the sweeps continue on those rows and columns alone (deflation), accumulating into
-// the matching columns of V.
-// One sweep is recorded as a HIP graph (rounds, then a fill kernel and the column check: no
-// memset node) and replayed per sweep when caches is given (one graph per order and buffer);
-// a graph is re-recorded when its sizes or buffers change.
+// V (device, mp x mp, ld mp) eigenvectors; work: jacobi_work(mp) complex.
+// One sweep is recorded as a HIP graph (rounds, then a fill kernel and the check: no memset
+// node) and replayed per sweep when cache is given; the graph is re-recorded when the sizes
+// or buffers change.
 struct JacobiGraph {
   void* graph = nullptr;
   void* exec = nullptr;
   int mp = 0;
-  int mpv = 0;
   const void* A0 = nullptr;
   const void* V = nullptr;
   const void* flag = nullptr;
-  const void* cmap = nullptr;
-  const void* colflag = nullptr;
   JacobiGraph() = default;
   JacobiGraph(const JacobiGraph&) = delete;
   JacobiGraph& operator=(const JacobiGraph&) = delete;
   ~JacobiGraph();
 };
-typedef std::map<int, JacobiGraph> JacobiGraphs;
 // mp = padded order (a multiple of 32, >= m; rows/columns beyond m are decoupled and sort
 // last).
 int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* dflag,
-                int max_sweeps, JacobiGraphs* caches, int mp);
+                int max_sweeps, JacobiGraph* cache, int mp);
 inline int jacobi_order(int m) { return (m + 31) / 32 * 32; }
-// Deflation starts once the active columns (rounded up to 32) are at most
-// kJacobiDeflNum / kJacobiDeflDen of the current order (measured against 3/4 and 7/8 on
-// config 2: within 3 % of each other).
-constexpr int kJacobiDeflNum = 1, kJacobiDeflDen = 2;
-// Largest compacted order at padded order mp.
-inline size_t jacobi_defl_max(int mp) { return (size_t)mp * kJacobiDeflNum / kJacobiDeflDen; }
 // Complex entries of jacobi_eigh's work array at padded order mp.
-inline size_t jacobi_work(int mp) {
-  return (size_t)mp * mp + 32 * (size_t)mp + 40 + (5 * (size_t)mp + 3) / 4 +
-         2 * jacobi_defl_max(mp) * jacobi_defl_max(mp);
-}
+inline size_t jacobi_work(int mp) { return (size_t)mp * mp + 32 * (size_t)mp + 40; }
 // Padded order used by callers that record sweeps for several nearby sizes.
 inline int jacobi_order_quantized(int m) { return jacobi_order(m); }
 // Stable ascending sort of d; Wout = V[:, order] (first m columns), lam = d[order].

@@ -305,16 +305,12 @@ __global__ __launch_bounds__(256) void jacobi_inner_kernel(zd* __restrict__ H, i
   }
 }
 
-// grid (npair, npair + mpv / JP), 1024 threads (one output entry each).  y < npair: H tiles
+// grid (npair, npair + mp / JP), 1024 threads (one output entry each).  y < npair: H tiles
 // P = y < Q = x: X = U_P^H H[P, Q] U_Q is written to H[P, Q] and X^H to H[Q, P] (the
 // transformed matrix stays exactly Hermitian; blocks with y >= x return at once).
-// y >= npair: V rows JP (y - npair) .. + JP - 1 against column pair Q = x.  H has order mp;
-// V has order mpv, and after deflation H is a compacted part of the problem whose index i is
-// column cmap[i] of V (cmap null: the identity).
+// y >= npair: V rows JP (y - npair) .. + JP - 1 against column pair Q = x.
 __global__ __launch_bounds__(1024) void jacobi_apply_kernel(zd* __restrict__ H, zd* __restrict__ V,
-                                                            int mp, int mpv,
-                                                            const int* __restrict__ cmap,
-                                                            int round,
+                                                            int mp, int round,
                                                             const zd* __restrict__ Ubuf) {
   __shared__ zd Ts[JP][JP + 1];
   __shared__ zd Uq[JP][JP + 1];
@@ -332,8 +328,7 @@ __global__ __launch_bounds__(1024) void jacobi_apply_kernel(zd* __restrict__ H, 
   const int c = t % JP, r = t / JP;
   const int gc = pair_index(c, Iq, Jq);
   const int gr = isH ? pair_index(r, Ip, Jp) : r0 + r;
-  const long at = isH ? gr + (long)gc * mp : gr + (long)(cmap ? cmap[gc] : gc) * mpv;
-  Ts[r][c] = M[at];
+  Ts[r][c] = M[gr + (long)gc * mp];
   Uq[r][c] = Ubuf[(long)x * JP * JP + r + c * JP];
   if (isH) Up[r][c] = Ubuf[(long)y * JP * JP + r + c * JP];
   __syncthreads();
@@ -349,47 +344,19 @@ __global__ __launch_bounds__(1024) void jacobi_apply_kernel(zd* __restrict__ H, 
     for (int j = 0; j < JP; ++j) acc = zadd(acc, zmul(zconj(Up[j][r]), Ts[j][c]));
     H[gc + (long)gr * mp] = zconj(acc);
   }
-  M[at] = acc;
+  M[gr + (long)gc * mp] = acc;
 }
 
-// One workgroup per column q: colflag[q] = 1 when an off-diagonal entry of column q (and so
-// of row q: H stays exactly Hermitian) is above the convergence floor; *flag is or-ed with it.
-__global__ __launch_bounds__(256) void jacobi_colcheck_kernel(const zd* __restrict__ H, int mp,
-                                                              const double* __restrict__ tolp,
-                                                              int* flag, int* colflag) {
-  const int q = blockIdx.x;
-  const double hqq = H[q + (long)q * mp].x;
-  int any = 0;
-  for (int p = threadIdx.x; p < mp; p += 256) {
-    if (p == q) continue;
-    const zd hpq = H[p + (long)q * mp];
-    const double a = sqrt(hpq.x * hpq.x + hpq.y * hpq.y);
-    const double hpp = H[p + (long)p * mp].x;
-    if (!(a == 0.0 || a <= 1e-17 * sqrt(fabs(hpp * hqq)) || a <= tolp[1])) any = 1;
-  }
-  any = __syncthreads_or(any);
-  if (threadIdx.x == 0) {
-    colflag[q] = any;
-    if (any) atomicOr(flag, 1);
-  }
-}
-
-// Deflation: Hn (mn x mn) = Hc[sel, sel].
-__global__ void jacobi_gather_kernel(const zd* __restrict__ Hc, int mc, const int* __restrict__ sel,
-                                     int mn, zd* __restrict__ Hn) {
+__global__ void jacobi_check_kernel(const zd* __restrict__ H, int mp, const double* __restrict__ tolp,
+                                    int* flag) {
   long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (idx >= (long)mn * mn) return;
-  const int i = (int)(idx % mn), j = (int)(idx / mn);
-  Hn[idx] = Hc[sel[i] + (long)sel[j] * mc];
-}
-
-// Final eigenvalues of the rows of Hc (order mc) that leave the iteration: d[cmap[i]] =
-// Hc[i][i] for every i with keep[i] == 0 (keep null: every i).
-__global__ void jacobi_diag_out_kernel(const zd* __restrict__ Hc, int mc, const int* __restrict__ cmap,
-                                       const int* __restrict__ keep, double* __restrict__ d) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= mc || (keep && keep[i])) return;
-  d[cmap ? cmap[i] : i] = Hc[i + (long)i * mc].x;
+  if (idx >= (long)mp * mp) return;
+  int p = (int)(idx % mp), q = (int)(idx / mp);
+  if (p >= q) return;
+  zd hpq = H[p + (long)q * mp];
+  double a = sqrt(hpq.x * hpq.x + hpq.y * hpq.y);
+  double hpp = H[p + (long)p * mp].x, hqq = H[q + (long)q * mp].x;
+  if (!(a == 0.0 || a <= 1e-17 * sqrt(fabs(hpp * hqq)) || a <= tolp[1])) atomicOr(flag, 1);
 }
 
 // tol[0] = eps ||H||_F (rotation floor) and tol[1] = 4 eps ||H||_F (convergence test) over the
@@ -651,21 +618,20 @@ void upper_inverse(hipStream_t s, const zd* R, int m, int ldr, zd* Rinv, int ldi
 }
 
 __global__ void zero_int_kernel(int* p) { p[0] = 0; }
-// One sweep over the current matrix H (order mc; nb - 1 outer rounds of an inner kernel and an
-// apply kernel, in place, the rotations accumulated into columns cmap of V, order mpv)
-// followed by the column check, either launched directly or recorded into a graph by stream
+// One sweep (nb - 1 outer rounds of an inner kernel and an apply kernel, in place) followed
+// by the convergence check, either launched directly or recorded into a graph by stream
 // capture.
-static void jacobi_sweep_launches(hipStream_t s, zd* H, int mc, zd* V, int mpv, const int* cmap,
-                                  zd* Ubuf, int* dflag, int* colflag, const double* tolp) {
-  const int nb = mc / JB, npair = nb / 2;
+static void jacobi_sweep_launches(hipStream_t s, zd* A, zd* V, zd* Ubuf, int mp, int* dflag,
+                                  const double* tolp) {
+  const int nb = mp / JB, npair = nb / 2;
   for (int r = 0; r < nb - 1; ++r) {
-    hipLaunchKernelGGL(jacobi_inner_kernel, dim3(npair), dim3(256), 0, s, H, mc, r, Ubuf, tolp);
-    hipLaunchKernelGGL(jacobi_apply_kernel, dim3(npair, npair + mpv / JP), dim3(1024), 0, s, H, V,
-                       mc, mpv, cmap, r, (const zd*)Ubuf);
+    hipLaunchKernelGGL(jacobi_inner_kernel, dim3(npair), dim3(256), 0, s, A, mp, r, Ubuf, tolp);
+    hipLaunchKernelGGL(jacobi_apply_kernel, dim3(npair, npair + mp / JP), dim3(1024), 0, s, A, V,
+                       mp, r, (const zd*)Ubuf);
   }
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, dflag);
-  hipLaunchKernelGGL(jacobi_colcheck_kernel, dim3(mc), dim3(256), 0, s, H, mc, tolp, dflag,
-                     colflag);
+  hipLaunchKernelGGL(jacobi_check_kernel, grid1((long)mp * mp), dim3(256), 0, s, A, mp, tolp,
+                     dflag);
 }
 
 JacobiGraph::~JacobiGraph() {
@@ -673,146 +639,56 @@ JacobiGraph::~JacobiGraph() {
   if (graph) (void)hipGraphDestroy((hipGraph_t)graph);
 }
 
-namespace {
-struct JacobiLayout {
-  zd* A0;
-  zd* Ubuf;
-  double* dwork;
-  double* tolp;
-  int* colflag;
-  int* sel;
-  int* keep;
-  int* cmap[2];
-  zd* Hc[2];
-};
-JacobiLayout jacobi_layout(zd* work, int mp) {
-  JacobiLayout L;
-  L.A0 = work;
-  L.Ubuf = work + (long)mp * mp;
-  L.dwork = (double*)(L.Ubuf + (long)mp * JP);
-  L.tolp = L.dwork + 64;
-  int* ints = (int*)(L.Ubuf + (long)mp * JP + 40);
-  L.colflag = ints;
-  L.sel = ints + mp;
-  L.keep = ints + 2 * mp;
-  L.cmap[0] = ints + 3 * mp;
-  L.cmap[1] = ints + 4 * mp;
-  zd* hc = L.Ubuf + (long)mp * JP + 40 + (5L * mp + 3) / 4;
-  const long half = (long)jacobi_defl_max(mp) * (long)jacobi_defl_max(mp);
-  L.Hc[0] = hc;
-  L.Hc[1] = hc + half;
-  return L;
-}
-
-// The graph for one sweep at order mc on buffers (H, cmap), recorded on first use and whenever
-// the sizes or buffers differ from the recorded ones.
-hipGraphExec_t jacobi_graph(hipStream_t s, JacobiGraph& g, zd* H, int mc, zd* V, int mpv,
-                            const int* cmap, zd* Ubuf, int* dflag, int* colflag,
-                            const double* tolp) {
-  if (g.exec && g.mp == mc && g.A0 == H && g.V == V && g.flag == dflag && g.mpv == mpv &&
-      g.cmap == cmap && g.colflag == colflag)
-    return (hipGraphExec_t)g.exec;
-  if (g.exec) FEAST_HIP(hipGraphExecDestroy((hipGraphExec_t)g.exec));
-  if (g.graph) FEAST_HIP(hipGraphDestroy((hipGraph_t)g.graph));
-  g.exec = g.graph = nullptr;
-  hipGraph_t gr = nullptr;
-  FEAST_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  jacobi_sweep_launches(s, H, mc, V, mpv, cmap, Ubuf, dflag, colflag, tolp);
-  FEAST_HIP(hipStreamEndCapture(s, &gr));
-  hipGraphExec_t ge = nullptr;
-  FEAST_HIP(hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0));
-  g.graph = gr;
-  g.exec = ge;
-  g.mp = mc;
-  g.A0 = H;
-  g.V = V;
-  g.flag = dflag;
-  g.mpv = mpv;
-  g.cmap = cmap;
-  g.colflag = colflag;
-  return ge;
-}
-}  // namespace
-
 int jacobi_eigh(hipStream_t s, zd* H, int m, double* d, zd* V, zd* work, int* dflag,
-                int max_sweeps, JacobiGraphs* caches, int mp) {
+                int max_sweeps, JacobiGraph* cache, int mp) {
   // work: jacobi_work(mp) complex: the working matrix (mp^2), the outer round's block-pair
-  // unitaries (mp / JP of JP x JP), 64 partial sums and tol as doubles, five int arrays of mp
-  // (column flags, selection, membership, two column maps) and two compacted matrices of at
-  // most (mp / 2)^2; V is mp x mp.
+  // unitaries (mp / JP of JP x JP), then 64 partial sums and tol as doubles; V is mp x mp.
   if (mp < jacobi_order(m) || mp % JP)
     throw HipError{hipErrorInvalidValue, "jacobi_eigh: padded order must be a multiple of 32 >= m"};
-  const JacobiLayout L = jacobi_layout(work, mp);
-  hipLaunchKernelGGL(jacobi_init_kernel, grid1((long)mp * mp), dim3(256), 0, s, H, m, mp, L.A0, V);
-  hipLaunchKernelGGL(fro_partial_kernel, dim3(64), dim3(256), 0, s, H, (long)m * m, L.dwork);
-  hipLaunchKernelGGL(fro_final_kernel, dim3(1), dim3(64), 0, s, L.dwork, 64, L.tolp);
+  zd* A0 = work;
+  zd* Ubuf = work + (long)mp * mp;
+  double* dwork = (double*)(Ubuf + (long)mp * JP);
+  double* tolp = dwork + 64;
+  hipLaunchKernelGGL(jacobi_init_kernel, grid1((long)mp * mp), dim3(256), 0, s, H, m, mp, A0, V);
+  hipLaunchKernelGGL(fro_partial_kernel, dim3(64), dim3(256), 0, s, H, (long)m * m, dwork);
+  hipLaunchKernelGGL(fro_final_kernel, dim3(1), dim3(64), 0, s, dwork, 64, tolp);
   FEAST_LAUNCH_CHECK();
-  // Deflation: once the columns with an off-diagonal entry above the convergence floor
-  // (rounded up to a multiple of 32) are at most half of the current order, their rows and
-  // columns are gathered into a smaller matrix and the sweeps go on there, accumulating into
-  // the matching columns of V; every other row has converged (its off-diagonal entries can
-  // no longer change its eigenvalue beyond the floor), and its diagonal entry is its
-  // eigenvalue.
-  zd* Hcur = L.A0;
-  int mc = mp, region = 0, hreg = -1;  // hreg: compacted buffer holding Hcur (-1: A0)
-  const int* cmap_dev = nullptr;
-  std::vector<int> cmap(mp), flags(mp), sel, keep, cmap_next;
-  for (int i = 0; i < mp; ++i) cmap[i] = i;
+  hipGraphExec_t exec = nullptr;
+  if (cache && s) {  // the legacy null stream cannot be captured
+    if (!(cache->exec && cache->mp == mp && cache->A0 == A0 && cache->V == V &&
+          cache->flag == dflag)) {
+      if (cache->exec) FEAST_HIP(hipGraphExecDestroy((hipGraphExec_t)cache->exec));
+      if (cache->graph) FEAST_HIP(hipGraphDestroy((hipGraph_t)cache->graph));
+      cache->exec = cache->graph = nullptr;
+      hipGraph_t g = nullptr;
+      FEAST_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      jacobi_sweep_launches(s, A0, V, Ubuf, mp, dflag, tolp);
+      FEAST_HIP(hipStreamEndCapture(s, &g));
+      hipGraphExec_t ge = nullptr;
+      FEAST_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+      cache->graph = g;
+      cache->exec = ge;
+      cache->mp = mp;
+      cache->A0 = A0;
+      cache->V = V;
+      cache->flag = dflag;
+    }
+    exec = (hipGraphExec_t)cache->exec;
+  }
   int sweeps = 0;
   bool converged = false;
   for (; sweeps < max_sweeps && !converged; ++sweeps) {
-    int* colflag = L.colflag;
-    if (caches && s) {  // the legacy null stream cannot be captured
-      const int key = (hreg < 0) ? mp : -(2 * mc + hreg) - 1;
-      hipGraphExec_t ge = jacobi_graph(s, (*caches)[key], Hcur, mc, V, mp, cmap_dev, L.Ubuf,
-                                       dflag, colflag, L.tolp);
-      FEAST_HIP(hipGraphLaunch(ge, s));
-    } else {
-      jacobi_sweep_launches(s, Hcur, mc, V, mp, cmap_dev, L.Ubuf, dflag, colflag, L.tolp);
-    }
+    if (exec) FEAST_HIP(hipGraphLaunch(exec, s));
+    else jacobi_sweep_launches(s, A0, V, Ubuf, mp, dflag, tolp);
     FEAST_LAUNCH_CHECK();
     int h = 0;
     FEAST_HIP(hipMemcpyAsync(&h, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
-    FEAST_HIP(hipMemcpyAsync(flags.data(), colflag, sizeof(int) * mc, hipMemcpyDeviceToHost, s));
     FEAST_HIP(hipStreamSynchronize(s));
     converged = (h == 0);
-    if (converged) break;
-    int count = 0;
-    for (int i = 0; i < mc; ++i) count += flags[i] != 0;
-    const int mn = (count + JP - 1) / JP * JP;
-    if ((long)mn * kJacobiDeflDen > (long)mc * kJacobiDeflNum) continue;
-    // active columns first, then converged ones up to a multiple of 32
-    sel.clear();
-    keep.assign(mc, 0);
-    for (int i = 0; i < mc; ++i)
-      if (flags[i]) sel.push_back(i);
-    for (int i = 0; i < mc && (int)sel.size() < mn; ++i)
-      if (!flags[i]) sel.push_back(i);
-    for (int i : sel) keep[i] = 1;
-    cmap_next.resize(mn);
-    for (int i = 0; i < mn; ++i) cmap_next[i] = cmap[sel[i]];
-    int* cm = L.cmap[region];
-    zd* Hn = L.Hc[region];
-    FEAST_HIP(hipMemcpyAsync(L.sel, sel.data(), sizeof(int) * mn, hipMemcpyHostToDevice, s));
-    FEAST_HIP(hipMemcpyAsync(L.keep, keep.data(), sizeof(int) * mc, hipMemcpyHostToDevice, s));
-    FEAST_HIP(hipMemcpyAsync(cm, cmap_next.data(), sizeof(int) * mn, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(jacobi_diag_out_kernel, grid1(mc), dim3(256), 0, s, Hcur, mc, cmap_dev,
-                       L.keep, d);
-    hipLaunchKernelGGL(jacobi_gather_kernel, grid1((long)mn * mn), dim3(256), 0, s, Hcur, mc,
-                       L.sel, mn, Hn);
-    FEAST_LAUNCH_CHECK();
-    FEAST_HIP(hipStreamSynchronize(s));  // the host arrays above are reused
-    Hcur = Hn;
-    mc = mn;
-    cmap_dev = cm;
-    cmap.assign(cmap_next.begin(), cmap_next.end());
-    hreg = region;
-    region ^= 1;
   }
-  hipLaunchKernelGGL(jacobi_diag_out_kernel, grid1(mc), dim3(256), 0, s, Hcur, mc, cmap_dev,
-                     nullptr, d);
+  hipLaunchKernelGGL(diag_kernel, grid1(mp), dim3(256), 0, s, A0, mp, d);
   FEAST_LAUNCH_CHECK();
-  return converged ? sweeps + 1 : -1;
+  return converged ? sweeps : -1;
 }
 
 void sort_eigen(hipStream_t s, const double* d, const zd* V, int m, int mp, double* lam, zd* W,
