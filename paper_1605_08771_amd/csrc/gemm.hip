@@ -53,17 +53,22 @@ constexpr int BM = 64, BN = 64, BK = 16, NT = 256, PAD = 1;
 #endif
 
 
+// BK: K-tile depth (complex entries) of the staged operand tiles (16 for both precisions; a
+// 32-deep FP32 tile needs 248-255 VGPRs and twice the LDS, two workgroups per CU instead of
+// three, and measured 8-13 % slower on the hot shapes).
 template <typename T>
 struct CT;
 template <>
 struct CT<double> {
   typedef double2 v2;
   typedef d4 acc;
+  static constexpr int BK = 16;
 };
 template <>
 struct CT<float> {
   typedef float2 v2;
   typedef f4 acc;
+  static constexpr int BK = 16;
 };
 
 __device__ inline d4 mfma(double a, double b, d4 c) {
@@ -109,8 +114,8 @@ struct Args {
 template <typename T, int OPA, int OPB, bool G3>
 __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int prob, int b1,
                                           int b2, int i0, int j0,
-                                          typename CT<T>::v2 (*As)[BK][BM + PAD],
-                                          typename CT<T>::v2 (*Bs)[BK][BN + PAD]) {
+                                          typename CT<T>::v2 (*As)[CT<T>::BK][BM + PAD],
+                                          typename CT<T>::v2 (*Bs)[CT<T>::BK][BN + PAD]) {
   typedef typename CT<T>::v2 v2;
   typedef typename CT<T>::acc accv;
   const int t = threadIdx.x;
@@ -139,7 +144,10 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
     K = ke - kb;
   }
 
-  v2 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+  // Each thread stages NL entries of each operand per K-tile: along the rows (64 per K column)
+  // when the rows are contiguous in storage, along K (BK per row) when K is.
+  constexpr int BK = CT<T>::BK, NL = BK / 4, KR = NT / BK;
+  v2 ra[NL], rb[NL];
 
 #define FEAST_LOAD_A(R, DST)                                                         \
   {                                                                                  \
@@ -148,7 +156,7 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
       int gi = i0 + i, gk = k0 + k;                                                  \
       DST = ldc_<v2, false>(A + gi + (long)gk * lda, gi < M && gk < K);              \
     } else {                                                                         \
-      int k = t & 15, i = (t >> 4) + 16 * (R);                                       \
+      int k = t % BK, i = t / BK + KR * (R);                                         \
       int gi = i0 + i, gk = k0 + k;                                                  \
       DST = ldc_<v2, OPA == OP_C>(A + gk + (long)gi * lda, gi < M && gk < K);        \
     }                                                                                \
@@ -156,7 +164,7 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
 #define FEAST_LOAD_B(R, DST)                                                         \
   {                                                                                  \
     if (OPB == OP_N) {                                                               \
-      int k = t & 15, j = (t >> 4) + 16 * (R);                                       \
+      int k = t % BK, j = t / BK + KR * (R);                                         \
       int gj = j0 + j, gk = k0 + k;                                                  \
       DST = ldc_<v2, false>(B + gk + (long)gj * ldb, gj < N && gk < K);              \
     } else {                                                                         \
@@ -165,24 +173,23 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
       DST = ldc_<v2, OPB == OP_C>(B + gj + (long)gk * ldb, gj < N && gk < K);        \
     }                                                                                \
   }
-#define FEAST_LOAD_TILE_INTO(K0, A0, A1, A2, A3, B0, B1, B2, B3)                    \
+#define FEAST_LOAD_TILE_INTO(K0, RA, RB)                                             \
   {                                                                                  \
     const int k0 = (K0);                                                             \
-    FEAST_LOAD_A(0, A0) FEAST_LOAD_A(1, A1) FEAST_LOAD_A(2, A2) FEAST_LOAD_A(3, A3)  \
-    FEAST_LOAD_B(0, B0) FEAST_LOAD_B(1, B1) FEAST_LOAD_B(2, B2) FEAST_LOAD_B(3, B3)  \
+    _Pragma("unroll") for (int r_ = 0; r_ < NL; ++r_) FEAST_LOAD_A(r_, RA[r_])        \
+    _Pragma("unroll") for (int r_ = 0; r_ < NL; ++r_) FEAST_LOAD_B(r_, RB[r_])        \
   }
 #define FEAST_STORE_AB(R, SA, SB)                                                    \
   {                                                                                  \
     if (OPA == OP_N) As[buf_][(t >> 6) + 4 * (R)][t & 63] = SA;                      \
-    else As[buf_][t & 15][(t >> 4) + 16 * (R)] = SA;                                 \
-    if (OPB == OP_N) Bs[buf_][t & 15][(t >> 4) + 16 * (R)] = SB;                     \
+    else As[buf_][t % BK][t / BK + KR * (R)] = SA;                                   \
+    if (OPB == OP_N) Bs[buf_][t % BK][t / BK + KR * (R)] = SB;                       \
     else Bs[buf_][(t >> 6) + 4 * (R)][t & 63] = SB;                                  \
   }
-#define FEAST_STORE_TILE_FROM(BUF, A0, A1, A2, A3, B0, B1, B2, B3)                  \
+#define FEAST_STORE_TILE_FROM(BUF, RA, RB)                                           \
   {                                                                                  \
     const int buf_ = (BUF);                                                          \
-    FEAST_STORE_AB(0, A0, B0) FEAST_STORE_AB(1, A1, B1)                              \
-    FEAST_STORE_AB(2, A2, B2) FEAST_STORE_AB(3, A3, B3)                              \
+    _Pragma("unroll") for (int r_ = 0; r_ < NL; ++r_) FEAST_STORE_AB(r_, RA[r_], RB[r_]) \
   }
   // G3 (FP32): three real products per complex one (Gauss): p1 = re re, p2 = im im,
   // p3 = (re + im)(re + im); the epilogue forms re = p1 - p2, im = p3 - p1 - p2.
@@ -256,17 +263,16 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
     // prefetch distance one (FP64 with three accumulator sets: the second register set of
     // the distance-two pipeline does not fit beside them)
     if (nkt > 0) {
-      FEAST_LOAD_TILE_INTO(0, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)
-      FEAST_STORE_TILE_FROM(0, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)
+      FEAST_LOAD_TILE_INTO(0, ra, rb)
+      FEAST_STORE_TILE_FROM(0, ra, rb)
     }
     __syncthreads();
 #define FEAST_KLOOP1(CHK)                                                            \
   for (int kt = 0; kt < nkt; ++kt) {                                                 \
     const int cur = kt & 1;                                                          \
-    if (kt + 1 < nkt)                                                                \
-      FEAST_LOAD_TILE_INTO((kt + 1) * BK, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)    \
+    if (kt + 1 < nkt) FEAST_LOAD_TILE_INTO((kt + 1) * BK, ra, rb)                    \
     FEAST_COMPUTE(cur, CHK)                                                          \
-    if (kt + 1 < nkt) FEAST_STORE_TILE_FROM(cur ^ 1, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3) \
+    if (kt + 1 < nkt) FEAST_STORE_TILE_FROM(cur ^ 1, ra, rb)                         \
     __syncthreads();                                                                 \
   }
     if (i0 + BM <= M && j0 + BN <= N) {
@@ -276,26 +282,24 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
     }
 #undef FEAST_KLOOP1
   } else {
-  v2 qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3;
+  v2 qa[NL], qb[NL];
   // prefetch distance two: tile kt+2 is in flight while tile kt is multiplied
   if (nkt > 0) {
-    FEAST_LOAD_TILE_INTO(0, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)
-    FEAST_STORE_TILE_FROM(0, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)
+    FEAST_LOAD_TILE_INTO(0, ra, rb)
+    FEAST_STORE_TILE_FROM(0, ra, rb)
   }
-  if (nkt > 1) FEAST_LOAD_TILE_INTO(BK, qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3)
+  if (nkt > 1) FEAST_LOAD_TILE_INTO(BK, qa, qb)
   __syncthreads();
 #define FEAST_KLOOP(CHK)                                                             \
   for (int kt = 0; kt < nkt; kt += 2) {                                              \
-    if (kt + 2 < nkt)                                                                \
-      FEAST_LOAD_TILE_INTO((kt + 2) * BK, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3)    \
+    if (kt + 2 < nkt) FEAST_LOAD_TILE_INTO((kt + 2) * BK, ra, rb)                    \
     FEAST_COMPUTE(0, CHK)                                                            \
-    if (kt + 1 < nkt) FEAST_STORE_TILE_FROM(1, qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3) \
+    if (kt + 1 < nkt) FEAST_STORE_TILE_FROM(1, qa, qb)                               \
     __syncthreads();                                                                 \
     if (kt + 1 >= nkt) break;                                                        \
-    if (kt + 3 < nkt)                                                                \
-      FEAST_LOAD_TILE_INTO((kt + 3) * BK, qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3)    \
+    if (kt + 3 < nkt) FEAST_LOAD_TILE_INTO((kt + 3) * BK, qa, qb)                    \
     FEAST_COMPUTE(1, CHK)                                                            \
-    if (kt + 2 < nkt) FEAST_STORE_TILE_FROM(0, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3) \
+    if (kt + 2 < nkt) FEAST_STORE_TILE_FROM(0, ra, rb)                               \
     __syncthreads();                                                                 \
   }
   // The branch is uniform over the workgroup (it depends on the tile origin only), so both
@@ -347,8 +351,8 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
 template <typename T, int OPA0, int OPA1, int OPB, bool G3>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void gemm_kernel(const Args<typename CT<T>::v2> a) {
   typedef typename CT<T>::v2 v2;
-  __shared__ v2 As[2][BK][BM + PAD];
-  __shared__ v2 Bs[2][BK][BN + PAD];
+  __shared__ v2 As[2][CT<T>::BK][BM + PAD];
+  __shared__ v2 Bs[2][CT<T>::BK][BN + PAD];
   // XCD-aware order: linear id L runs on XCD L % 8; each XCD gets a contiguous range.
   const long per = (long)a.tilesM * a.tilesN;
   const long total = (long)gridDim.x * gridDim.y * gridDim.z;
