@@ -133,8 +133,10 @@ def test_c2_trace_vs_oracle_fixture(fe, c2):
     each of the first iterations of FEAST (FP64, filter-value test on), against the oracle's
     trace on the same seeded input (tests/golden/c2_oracle_trace.txt, written by
     make_c2_oracle_trace.py from the oracle alone).  The two sides orthonormalize differently
-    (Cholesky-QR against the Gram route) and round differently, so the traces agree to a
-    relative 1e-3 while the residual is far above the rounding floor."""
+    (Cholesky-QR against the Gram route) and round differently, and the difference grows over
+    the iterations (measured: 1.1e-13 relative at the first, at most 5.3e-7 over the twelve),
+    so the traces are compared to a relative 1e-5 while the residual is far above the
+    rounding floor."""
     import torch
     g = _golden("c2_oracle_trace.txt")
     its = int(g["iterations"])
@@ -145,7 +147,7 @@ def test_c2_trace_vs_oracle_fixture(fe, c2):
     torch.cuda.synchronize()
     fe.invalidate()
     assert out["status"] == 1 and out["iters"] == its
-    np.testing.assert_allclose(out["trace"], ref, rtol=1e-3, atol=0)
+    np.testing.assert_allclose(out["trace"], ref, rtol=1e-5, atol=0)
 
 
 def test_c3_mixed_solve_full_size(fe):
