@@ -12,6 +12,23 @@ int pick_np(int n, int prec) {  // the padding the solver uses (a multiple of th
   const int nbt = sweep_block(n, prec == 0 ? 0 : 1);
   return (n + nbt - 1) / nbt * nbt;
 }
+
+// Device scratch of one call, freed on every path out of it (hipFree waits for the device).
+struct DevMem {
+  void* p = nullptr;
+  explicit DevMem(size_t bytes) {
+    if (bytes) FEAST_HIP(hipMalloc(&p, bytes));
+  }
+  ~DevMem() {
+    if (p) (void)hipFree(p);
+  }
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  template <typename T>
+  T* as() const {
+    return (T*)p;
+  }
+};
 }  // namespace
 
 extern "C" int feast_kern_gemm(int prec, int opA, int opB, int M, int N, int K,
@@ -65,13 +82,11 @@ extern "C" int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, co
   if (!perm) return -8;
   try {
     hipStream_t s = (hipStream_t)hip_stream;
-    zd* zdev = nullptr;
-    void* wbuf = nullptr;
-    FEAST_HIP(hipMalloc(&zdev, sizeof(zd) * nc));
+    DevMem zbuf(sizeof(zd) * nc), wbuf(lu_work_bytes(np, nc));
+    zd* zdev = zbuf.as<zd>();
     FEAST_HIP(hipMemcpyAsync(zdev, z, sizeof(zd) * nc, hipMemcpyHostToDevice, s));
-    FEAST_HIP(hipMalloc(&wbuf, lu_work_bytes(np, nc)));
     LuWork w;
-    lu_work_carve(w, wbuf, np, nc);
+    lu_work_carve(w, wbuf.p, np, nc);
     w.column_steps = column_steps;
     if (prec == 0) {
       shift_matrices(s, A, lda, 0, n, np, zdev, nc, (zd*)LU, w.flag);
@@ -85,8 +100,6 @@ extern "C" int feast_kern_lu(int prec, const void* A, int lda, int n, int nc, co
     FEAST_HIP(hipMemcpyAsync(perm, w.perm, sizeof(int) * (size_t)nc * np, hipMemcpyDeviceToDevice, s));
     FEAST_HIP(hipMemcpyAsync(&flag, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
     FEAST_HIP(hipStreamSynchronize(s));
-    FEAST_HIP(hipFree(zdev));
-    FEAST_HIP(hipFree(wbuf));
     return flag ? 6 : 0;
   } catch (const HipError&) {
     return -101;
@@ -112,8 +125,8 @@ extern "C" int feast_kern_sweeps(int prec, int n, int nc, int m0, int sides, con
   try {
     hipStream_t s = (hipStream_t)hip_stream;
     const size_t esz = prec == 0 ? sizeof(zd) : sizeof(zf);
-    void* tmp = nullptr;
-    if (compute_inverses) FEAST_HIP(hipMalloc(&tmp, esz * (size_t)np * nbt));
+    DevMem tbuf(compute_inverses ? esz * (size_t)np * nbt : 0);
+    void* tmp = tbuf.p;
     if (prec == 0) {
       if (compute_inverses)
         tri_inverse_blocks_f64(s, (const zd*)LU, np, nc, nbt, (zd*)invL, (zd*)invU, (zd*)tmp);
@@ -127,7 +140,6 @@ extern "C" int feast_kern_sweeps(int prec, int n, int nc, int m0, int sides, con
                        (zf*)B, (zf*)Z);
     }
     FEAST_HIP(hipStreamSynchronize(s));
-    if (tmp) FEAST_HIP(hipFree(tmp));
     return 0;
   } catch (const HipError&) {
     return -101;
@@ -144,26 +156,16 @@ extern "C" int feast_kern_jacobi(const void* H, int m, double* d, void* W, void*
   try {
     hipStream_t s = (hipStream_t)hip_stream;
     const int mp = jacobi_order(m);
-    zd *Hc, *V, *work;
-    double *dd, *lam;
-    int *flag, *rank;
-    FEAST_HIP(hipMalloc(&Hc, sizeof(zd) * (size_t)m * m));
-    FEAST_HIP(hipMalloc(&V, sizeof(zd) * (size_t)mp * mp));
-    FEAST_HIP(hipMalloc(&work, sizeof(zd) * jacobi_work(mp)));
-    FEAST_HIP(hipMalloc(&dd, sizeof(double) * mp));
-    FEAST_HIP(hipMalloc(&flag, 256));
-    FEAST_HIP(hipMalloc(&rank, sizeof(int) * mp));
-    lam = d;
+    DevMem hbuf(sizeof(zd) * (size_t)m * m), vbuf(sizeof(zd) * (size_t)mp * mp),
+        wbuf(sizeof(zd) * jacobi_work(mp)), dbuf(sizeof(double) * mp), fbuf(256),
+        rbuf(sizeof(int) * mp);
+    zd* Hc = hbuf.as<zd>();
+    zd* V = vbuf.as<zd>();
     copy_matrix(s, (const zd*)H, m, Hc, m, m, m);
-    int sweeps = jacobi_eigh(s, Hc, m, dd, V, work, flag, 60, nullptr, mp);
-    sort_eigen(s, dd, V, m, mp, lam, (zd*)W, rank);
+    int sweeps = jacobi_eigh(s, Hc, m, dbuf.as<double>(), V, wbuf.as<zd>(), fbuf.as<int>(), 60,
+                             nullptr, mp);
+    sort_eigen(s, dbuf.as<double>(), V, m, mp, d, (zd*)W, rbuf.as<int>());
     FEAST_HIP(hipStreamSynchronize(s));
-    FEAST_HIP(hipFree(Hc));
-    FEAST_HIP(hipFree(V));
-    FEAST_HIP(hipFree(work));
-    FEAST_HIP(hipFree(dd));
-    FEAST_HIP(hipFree(flag));
-    FEAST_HIP(hipFree(rank));
     return sweeps;
   } catch (const HipError&) {
     return -101;
