@@ -425,17 +425,25 @@ __global__ __launch_bounds__(GT) void panel_group_short_kernel(
       sr[b][wave] = r;
     }
     __syncthreads();
+    // every wave reduces the GW per-wave candidates itself: lane l < GW takes wave l's, then
+    // lane shuffles (the merge order does not matter: larger value, then lower row)
     double bv = -1.0;
-    int br = 0x7fffffff, bw = 0;
-    for (int w2 = 0; w2 < GW; ++w2) {
-      const double ov = sv[b][w2];
-      const int orow = sr[b][w2];
-      if (ov > bv || (ov == bv && orow < br)) {
-        bv = ov;
-        br = orow;
-        bw = w2;
-      }
+    int br = 0x7fffffff;
+    if (lane < GW) {
+      bv = sv[b][lane];
+      br = sr[b][lane];
     }
+#pragma unroll
+    for (int off = GW / 2; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int orow = __shfl_xor(br, off);
+      argmax_merge(bv, br, ov, orow);
+    }
+    bv = __shfl(bv, 0);
+    br = __shfl(br, 0);
+    // the winning wave holds the pivot row in its slot: rows k + t + i GT sit in wave
+    // ((br - k) mod GT) / 64
+    const int bw = (br >= k && br < np) ? ((br - k) % GT) >> 6 : 0;
     const int c = k + g0 + j;
     const bool bad = !(bv > 0.0) || br < k || br >= np;  // zero column or non-finite values
     const int p = bad ? c : br;
