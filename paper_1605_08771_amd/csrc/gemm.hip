@@ -6,9 +6,13 @@
 // every MFMA flop is a useful flop of the 8-flop complex multiply-add.
 //
 // Tiling: 256 threads = 4 wave64s in a 2x2 grid, workgroup tile 64x64 complex outputs,
-// K-tile 16 complex, double-buffered LDS, and two register sets so that the global loads of
-// K-tile kt+2 are in flight while K-tile kt is multiplied (one tile of compute, ~4k cycles,
-// does not cover HBM latency under load); the kernel is held to two waves per SIMD.  Within a
+// K-tile 16 complex, double-buffered LDS.  FP32 tiles (about 120 VGPRs, 33 KB of LDS) run
+// four waves per SIMD with one register set: the global loads of K-tile kt+1 are in flight
+// while K-tile kt is multiplied, and the other resident workgroups cover the rest of the load
+// latency (measured 2-9 % faster on the hot shapes than three waves per SIMD with the loads
+// two K-tiles ahead).  FP64 tiles (66 KB of LDS: two workgroups per CU) run two waves per
+// SIMD with two register sets, loads two K-tiles ahead (one tile of compute, ~4k cycles, does
+// not cover HBM latency under load), one ahead in the three-product form.  Within a
 // 4-deep k step the MFMAs are issued so that eight independent accumulators separate the two
 // products that feed the same one.  Operands are staged k-major so that lanes 0..15
 // of an MFMA fetch read 16 consecutive entries; LDS rows are padded by one entry so that
@@ -55,7 +59,8 @@ constexpr int BM = 64, BN = 64, BK = 16, NT = 256, PAD = 1;
 
 // BK: K-tile depth (complex entries) of the staged operand tiles (16 for both precisions; a
 // 32-deep FP32 tile needs 248-255 VGPRs and twice the LDS, two workgroups per CU instead of
-// three, and measured 8-13 % slower on the hot shapes).
+// three, and measured 8-13 % slower on the hot shapes).  WAVES: waves per SIMD the kernel is
+// compiled for (the register budget: 128 VGPRs at four, 256 at two).
 template <typename T>
 struct CT;
 template <>
@@ -63,12 +68,14 @@ struct CT<double> {
   typedef double2 v2;
   typedef d4 acc;
   static constexpr int BK = 16;
+  static constexpr int WAVES = 2;
 };
 template <>
 struct CT<float> {
   typedef float2 v2;
   typedef f4 acc;
   static constexpr int BK = 16;
+  static constexpr int WAVES = 4;
 };
 
 __device__ inline d4 mfma(double a, double b, d4 c) {
@@ -243,7 +250,7 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
           }                                                                           \
       }                                                                               \
   }
-  constexpr bool PF1 = G3 && sizeof(T) == 8;
+  constexpr bool PF1 = G3 || sizeof(T) == 4;
   accv accr[2][2], acci[2][2], accs[2][2];
   // A 16 x 16 output block that lies entirely past M or N has nothing to compute; the test
   // is uniform over the wave, so skipping its MFMAs frees the matrix core for other waves.
@@ -260,8 +267,8 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
 
   const int nkt = (K + BK - 1) / BK;
   if constexpr (PF1) {
-    // prefetch distance one (FP64 with three accumulator sets: the second register set of
-    // the distance-two pipeline does not fit beside them)
+    // prefetch distance one (FP32 at four waves per SIMD; FP64 with three accumulator sets,
+    // where the second register set of the distance-two pipeline does not fit beside them)
     if (nkt > 0) {
       FEAST_LOAD_TILE_INTO(0, ra, rb)
       FEAST_STORE_TILE_FROM(0, ra, rb)
@@ -349,7 +356,7 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
 }
 
 template <typename T, int OPA0, int OPA1, int OPB, bool G3>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void gemm_kernel(const Args<typename CT<T>::v2> a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CT<T>::WAVES))) void gemm_kernel(const Args<typename CT<T>::v2> a) {
   typedef typename CT<T>::v2 v2;
   __shared__ v2 As[2][CT<T>::BK][BM + PAD];
   __shared__ v2 Bs[2][CT<T>::BK][BN + PAD];
