@@ -156,35 +156,39 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
   constexpr int BK = CT<T>::BK, NL = BK / 4, KR = NT / BK;
   v2 ra[NL], rb[NL];
 
-#define FEAST_LOAD_A(R, DST)                                                         \
+// G: bounds tests needed (false only for interior tiles whose K is a multiple of BK, where
+// every staged entry lies inside the operands; the loaded values are the same either way).
+#define FEAST_LOAD_A(R, DST, G)                                                      \
   {                                                                                  \
     if (OPA == OP_N) {                                                               \
       int i = t & 63, k = (t >> 6) + 4 * (R);                                        \
       int gi = i0 + i, gk = k0 + k;                                                  \
-      DST = ldc_<v2, false>(A + gi + (long)gk * lda, gi < M && gk < K);              \
+      DST = ldc_<v2, false>(A + gi + (long)gk * lda, !(G) || (gi < M && gk < K));    \
     } else {                                                                         \
       int k = t % BK, i = t / BK + KR * (R);                                         \
       int gi = i0 + i, gk = k0 + k;                                                  \
-      DST = ldc_<v2, OPA == OP_C>(A + gk + (long)gi * lda, gi < M && gk < K);        \
+      DST = ldc_<v2, OPA == OP_C>(A + gk + (long)gi * lda,                           \
+                                  !(G) || (gi < M && gk < K));                       \
     }                                                                                \
   }
-#define FEAST_LOAD_B(R, DST)                                                         \
+#define FEAST_LOAD_B(R, DST, G)                                                      \
   {                                                                                  \
     if (OPB == OP_N) {                                                               \
       int k = t % BK, j = t / BK + KR * (R);                                         \
       int gj = j0 + j, gk = k0 + k;                                                  \
-      DST = ldc_<v2, false>(B + gk + (long)gj * ldb, gj < N && gk < K);              \
+      DST = ldc_<v2, false>(B + gk + (long)gj * ldb, !(G) || (gj < N && gk < K));    \
     } else {                                                                         \
       int j = t & 63, k = (t >> 6) + 4 * (R);                                        \
       int gj = j0 + j, gk = k0 + k;                                                  \
-      DST = ldc_<v2, OPB == OP_C>(B + gj + (long)gk * ldb, gj < N && gk < K);        \
+      DST = ldc_<v2, OPB == OP_C>(B + gj + (long)gk * ldb,                           \
+                                  !(G) || (gj < N && gk < K));                       \
     }                                                                                \
   }
-#define FEAST_LOAD_TILE_INTO(K0, RA, RB)                                             \
+#define FEAST_LOAD_TILE_INTO(K0, RA, RB, G)                                          \
   {                                                                                  \
     const int k0 = (K0);                                                             \
-    _Pragma("unroll") for (int r_ = 0; r_ < NL; ++r_) FEAST_LOAD_A(r_, RA[r_])        \
-    _Pragma("unroll") for (int r_ = 0; r_ < NL; ++r_) FEAST_LOAD_B(r_, RB[r_])        \
+    _Pragma("unroll") for (int r_ = 0; r_ < NL; ++r_) FEAST_LOAD_A(r_, RA[r_], G)     \
+    _Pragma("unroll") for (int r_ = 0; r_ < NL; ++r_) FEAST_LOAD_B(r_, RB[r_], G)     \
   }
 #define FEAST_STORE_AB(R, SA, SB)                                                    \
   {                                                                                  \
@@ -266,55 +270,60 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
     }
 
   const int nkt = (K + BK - 1) / BK;
+  const bool interior = i0 + BM <= M && j0 + BN <= N;
   if constexpr (PF1) {
     // prefetch distance one (FP32 at four waves per SIMD; FP64 with three accumulator sets,
     // where the second register set of the distance-two pipeline does not fit beside them)
     if (nkt > 0) {
-      FEAST_LOAD_TILE_INTO(0, ra, rb)
+      FEAST_LOAD_TILE_INTO(0, ra, rb, true)
       FEAST_STORE_TILE_FROM(0, ra, rb)
     }
     __syncthreads();
-#define FEAST_KLOOP1(CHK)                                                            \
+#define FEAST_KLOOP1(CHK, G)                                                         \
   for (int kt = 0; kt < nkt; ++kt) {                                                 \
     const int cur = kt & 1;                                                          \
-    if (kt + 1 < nkt) FEAST_LOAD_TILE_INTO((kt + 1) * BK, ra, rb)                    \
+    if (kt + 1 < nkt) FEAST_LOAD_TILE_INTO((kt + 1) * BK, ra, rb, G)                 \
     FEAST_COMPUTE(cur, CHK)                                                          \
     if (kt + 1 < nkt) FEAST_STORE_TILE_FROM(cur ^ 1, ra, rb)                         \
     __syncthreads();                                                                 \
   }
-    if (i0 + BM <= M && j0 + BN <= N) {
-      FEAST_KLOOP1(0)
+    if (interior && K % BK == 0) {
+      FEAST_KLOOP1(0, false)
+    } else if (interior) {
+      FEAST_KLOOP1(0, true)
     } else {
-      FEAST_KLOOP1(1)
+      FEAST_KLOOP1(1, true)
     }
 #undef FEAST_KLOOP1
   } else {
   v2 qa[NL], qb[NL];
   // prefetch distance two: tile kt+2 is in flight while tile kt is multiplied
   if (nkt > 0) {
-    FEAST_LOAD_TILE_INTO(0, ra, rb)
+    FEAST_LOAD_TILE_INTO(0, ra, rb, true)
     FEAST_STORE_TILE_FROM(0, ra, rb)
   }
-  if (nkt > 1) FEAST_LOAD_TILE_INTO(BK, qa, qb)
+  if (nkt > 1) FEAST_LOAD_TILE_INTO(BK, qa, qb, true)
   __syncthreads();
-#define FEAST_KLOOP(CHK)                                                             \
+#define FEAST_KLOOP(CHK, G)                                                          \
   for (int kt = 0; kt < nkt; kt += 2) {                                              \
-    if (kt + 2 < nkt) FEAST_LOAD_TILE_INTO((kt + 2) * BK, ra, rb)                    \
+    if (kt + 2 < nkt) FEAST_LOAD_TILE_INTO((kt + 2) * BK, ra, rb, G)                 \
     FEAST_COMPUTE(0, CHK)                                                            \
     if (kt + 1 < nkt) FEAST_STORE_TILE_FROM(1, qa, qb)                               \
     __syncthreads();                                                                 \
     if (kt + 1 >= nkt) break;                                                        \
-    if (kt + 3 < nkt) FEAST_LOAD_TILE_INTO((kt + 3) * BK, qa, qb)                    \
+    if (kt + 3 < nkt) FEAST_LOAD_TILE_INTO((kt + 3) * BK, qa, qb, G)                 \
     FEAST_COMPUTE(1, CHK)                                                            \
     if (kt + 2 < nkt) FEAST_STORE_TILE_FROM(0, ra, rb)                               \
     __syncthreads();                                                                 \
   }
-  // The branch is uniform over the workgroup (it depends on the tile origin only), so both
-  // loops see the same barriers; only ragged edge tiles pay for the per-block tests.
-  if (i0 + BM <= M && j0 + BN <= N) {
-    FEAST_KLOOP(0)
+  // The branch is uniform over the workgroup (it depends on the tile origin and K only), so
+  // every loop sees the same barriers; only ragged edge tiles pay for the per-block tests.
+  if (interior && K % BK == 0) {
+    FEAST_KLOOP(0, false)
+  } else if (interior) {
+    FEAST_KLOOP(0, true)
   } else {
-    FEAST_KLOOP(1)
+    FEAST_KLOOP(1, true)
   }
   }
 #undef FEAST_KLOOP
