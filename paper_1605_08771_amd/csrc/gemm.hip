@@ -6,13 +6,15 @@
 // every MFMA flop is a useful flop of the 8-flop complex multiply-add.
 //
 // Tiling: 256 threads = 4 wave64s in a 2x2 grid, workgroup tile 64x64 complex outputs,
-// K-tile 16 complex, double-buffered LDS.  FP32 tiles (about 120 VGPRs, 33 KB of LDS) run
-// four waves per SIMD with one register set: the global loads of K-tile kt+1 are in flight
-// while K-tile kt is multiplied, and the other resident workgroups cover the rest of the load
-// latency (measured 2-9 % faster on the hot shapes than three waves per SIMD with the loads
-// two K-tiles ahead).  FP64 tiles (66 KB of LDS: two workgroups per CU) run two waves per
-// SIMD with two register sets, loads two K-tiles ahead (one tile of compute, ~4k cycles, does
-// not cover HBM latency under load), one ahead in the three-product form.  Within a
+// double-buffered LDS, one register set of staged operands: the global loads of K-tile kt+1
+// are in flight while K-tile kt is multiplied, and the other resident workgroups cover the
+// rest of their latency.  Occupancy is what hides it (measured against two register sets with
+// loads two K-tiles ahead at fewer waves): FP32 tiles (K-tile 16, about 120 VGPRs, 33 KB of
+// LDS) run four waves per SIMD, 2-9 % faster on the hot shapes than three; four-product FP64
+// tiles (K-tile 8, about 140 VGPRs, 33 KB) three, 2-4 % faster than two with a 16-deep K-tile;
+// three-product FP64 tiles (K-tile 16, about 180 VGPRs: a third accumulator set) two, where a
+// K-tile of 8 was 3 % slower.  Interior tiles whose K is a multiple of the K-tile load without
+// bounds tests.  Within a
 // 4-deep k step the MFMAs are issued so that eight independent accumulators separate the two
 // products that feed the same one.  Operands are staged k-major so that lanes 0..15
 // of an MFMA fetch read 16 consecutive entries; LDS rows are padded by one entry so that
@@ -43,39 +45,37 @@ thread_local bool g_z3m = false;
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, NT = 256, PAD = 1;
+constexpr int BM = 64, BN = 64, NT = 256, PAD = 1;
 
 // FEAST_GEMM_3M = 1: FP32 complex products as three real matrix-core products (Gauss's
 // method: 3 MFMAs per 16x16x4 complex step instead of 4, a quarter less matrix-core work; the
 // imaginary part is formed as a difference, with a normwise error bound a small multiple of
 // the four-product one).  0: the four-product form.  FP64 products use the three-product form
-// only inside a Z3mScope (the caller decides where its accuracy suffices); the FP64 tiles then
-// prefetch one K-tile ahead instead of two, since the third accumulator set and the second
-// register set of the deeper pipeline do not both fit at two waves per SIMD.
+// only inside a Z3mScope (the caller decides where its accuracy suffices).
 #ifndef FEAST_GEMM_3M
 #define FEAST_GEMM_3M 1
 #endif
 
 
-// BK: K-tile depth (complex entries) of the staged operand tiles (16 for both precisions; a
-// 32-deep FP32 tile needs 248-255 VGPRs and twice the LDS, two workgroups per CU instead of
-// three, and measured 8-13 % slower on the hot shapes).  WAVES: waves per SIMD the kernel is
-// compiled for (the register budget: 128 VGPRs at four, 256 at two).
+// bk: K-tile depth (complex entries) of the staged operand tiles, by precision and product
+// form (a 32-deep FP32 tile needs 248-255 VGPRs and twice the LDS, and measured 8-13 % slower
+// on the hot shapes).  waves: waves per SIMD the kernel is compiled for (the register budget:
+// 128 VGPRs at four, 168 at three, 256 at two).
 template <typename T>
 struct CT;
 template <>
 struct CT<double> {
   typedef double2 v2;
   typedef d4 acc;
-  static constexpr int BK = 16;
-  static constexpr int WAVES = 2;
+  static constexpr int bk(bool g3) { return g3 ? 16 : 8; }
+  static constexpr int waves(bool g3) { return g3 ? 2 : 3; }
 };
 template <>
 struct CT<float> {
   typedef float2 v2;
   typedef f4 acc;
-  static constexpr int BK = 16;
-  static constexpr int WAVES = 4;
+  static constexpr int bk(bool) { return 16; }
+  static constexpr int waves(bool) { return 4; }
 };
 
 __device__ inline d4 mfma(double a, double b, d4 c) {
@@ -121,8 +121,8 @@ struct Args {
 template <typename T, int OPA, int OPB, bool G3>
 __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int prob, int b1,
                                           int b2, int i0, int j0,
-                                          typename CT<T>::v2 (*As)[CT<T>::BK][BM + PAD],
-                                          typename CT<T>::v2 (*Bs)[CT<T>::BK][BN + PAD]) {
+                                          typename CT<T>::v2 (*As)[CT<T>::bk(G3)][BM + PAD],
+                                          typename CT<T>::v2 (*Bs)[CT<T>::bk(G3)][BN + PAD]) {
   typedef typename CT<T>::v2 v2;
   typedef typename CT<T>::acc accv;
   const int t = threadIdx.x;
@@ -153,7 +153,7 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
 
   // Each thread stages NL entries of each operand per K-tile: along the rows (64 per K column)
   // when the rows are contiguous in storage, along K (BK per row) when K is.
-  constexpr int BK = CT<T>::BK, NL = BK / 4, KR = NT / BK;
+  constexpr int BK = CT<T>::bk(G3), NL = BK / 4, KR = NT / BK;
   v2 ra[NL], rb[NL];
 
 // G: bounds tests needed (false only for interior tiles whose K is a multiple of BK, where
@@ -254,7 +254,6 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
           }                                                                           \
       }                                                                               \
   }
-  constexpr bool PF1 = G3 || sizeof(T) == 4;
   accv accr[2][2], acci[2][2], accs[2][2];
   // A 16 x 16 output block that lies entirely past M or N has nothing to compute; the test
   // is uniform over the wave, so skipping its MFMAs frees the matrix core for other waves.
@@ -271,49 +270,19 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
 
   const int nkt = (K + BK - 1) / BK;
   const bool interior = i0 + BM <= M && j0 + BN <= N;
-  if constexpr (PF1) {
-    // prefetch distance one (FP32 at four waves per SIMD; FP64 with three accumulator sets,
-    // where the second register set of the distance-two pipeline does not fit beside them)
-    if (nkt > 0) {
-      FEAST_LOAD_TILE_INTO(0, ra, rb, true)
-      FEAST_STORE_TILE_FROM(0, ra, rb)
-    }
-    __syncthreads();
-#define FEAST_KLOOP1(CHK, G)                                                         \
+  // Loads of K-tile kt+1 are in flight while K-tile kt is multiplied; the other resident
+  // workgroups cover the rest of their latency.
+  if (nkt > 0) {
+    FEAST_LOAD_TILE_INTO(0, ra, rb, true)
+    FEAST_STORE_TILE_FROM(0, ra, rb)
+  }
+  __syncthreads();
+#define FEAST_KLOOP(CHK, G)                                                          \
   for (int kt = 0; kt < nkt; ++kt) {                                                 \
     const int cur = kt & 1;                                                          \
     if (kt + 1 < nkt) FEAST_LOAD_TILE_INTO((kt + 1) * BK, ra, rb, G)                 \
     FEAST_COMPUTE(cur, CHK)                                                          \
     if (kt + 1 < nkt) FEAST_STORE_TILE_FROM(cur ^ 1, ra, rb)                         \
-    __syncthreads();                                                                 \
-  }
-    if (interior && K % BK == 0) {
-      FEAST_KLOOP1(0, false)
-    } else if (interior) {
-      FEAST_KLOOP1(0, true)
-    } else {
-      FEAST_KLOOP1(1, true)
-    }
-#undef FEAST_KLOOP1
-  } else {
-  v2 qa[NL], qb[NL];
-  // prefetch distance two: tile kt+2 is in flight while tile kt is multiplied
-  if (nkt > 0) {
-    FEAST_LOAD_TILE_INTO(0, ra, rb, true)
-    FEAST_STORE_TILE_FROM(0, ra, rb)
-  }
-  if (nkt > 1) FEAST_LOAD_TILE_INTO(BK, qa, qb, true)
-  __syncthreads();
-#define FEAST_KLOOP(CHK, G)                                                          \
-  for (int kt = 0; kt < nkt; kt += 2) {                                              \
-    if (kt + 2 < nkt) FEAST_LOAD_TILE_INTO((kt + 2) * BK, ra, rb, G)                 \
-    FEAST_COMPUTE(0, CHK)                                                            \
-    if (kt + 1 < nkt) FEAST_STORE_TILE_FROM(1, qa, qb)                               \
-    __syncthreads();                                                                 \
-    if (kt + 1 >= nkt) break;                                                        \
-    if (kt + 3 < nkt) FEAST_LOAD_TILE_INTO((kt + 3) * BK, qa, qb, G)                 \
-    FEAST_COMPUTE(1, CHK)                                                            \
-    if (kt + 2 < nkt) FEAST_STORE_TILE_FROM(0, ra, rb)                               \
     __syncthreads();                                                                 \
   }
   // The branch is uniform over the workgroup (it depends on the tile origin and K only), so
@@ -324,7 +293,6 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
     FEAST_KLOOP(0, true)
   } else {
     FEAST_KLOOP(1, true)
-  }
   }
 #undef FEAST_KLOOP
 #undef FEAST_LOAD_A
@@ -365,10 +333,10 @@ __device__ __forceinline__ void gemm_tile(const Args<typename CT<T>::v2>& a, int
 }
 
 template <typename T, int OPA0, int OPA1, int OPB, bool G3>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CT<T>::WAVES))) void gemm_kernel(const Args<typename CT<T>::v2> a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CT<T>::waves(G3)))) void gemm_kernel(const Args<typename CT<T>::v2> a) {
   typedef typename CT<T>::v2 v2;
-  __shared__ v2 As[2][CT<T>::BK][BM + PAD];
-  __shared__ v2 Bs[2][CT<T>::BK][BN + PAD];
+  __shared__ v2 As[2][CT<T>::bk(G3)][BM + PAD];
+  __shared__ v2 Bs[2][CT<T>::bk(G3)][BN + PAD];
   // XCD-aware order: linear id L runs on XCD L % 8; each XCD gets a contiguous range.
   const long per = (long)a.tilesM * a.tilesN;
   const long total = (long)gridDim.x * gridDim.y * gridDim.z;
