@@ -752,18 +752,19 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const zd* part, int n
   C[(i % M) + (i / M) * ldc] = acc;
 }
 
-// Workgroups of the FP64 op(N, N) GEMM kernel resident on the current device at once.
-int zgemm_resident_tiles() {
-  static std::atomic<int> cache[64];
+// Workgroups of the FP64 op(N, N) GEMM kernel resident on the current device at once, for
+// the product form that runs (g3: three real products, which holds fewer per CU).
+int zgemm_resident_tiles(bool g3) {
+  static std::atomic<int> cache[64][2];
   int dev = 0;
   FEAST_HIP(hipGetDevice(&dev));
-  std::atomic<int>* c = (dev >= 0 && dev < 64) ? &cache[dev] : nullptr;
+  std::atomic<int>* c = (dev >= 0 && dev < 64) ? &cache[dev][g3 ? 1 : 0] : nullptr;
   if (c && c->load() > 0) return c->load();
   int cus = 0, per_cu = 0;
   FEAST_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  FEAST_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, reinterpret_cast<const void*>(&gemm_kernel<double, OP_N, OP_N, OP_N, false>), NT,
-      0));
+  const void* k = g3 ? reinterpret_cast<const void*>(&gemm_kernel<double, OP_N, OP_N, OP_N, true>)
+                     : reinterpret_cast<const void*>(&gemm_kernel<double, OP_N, OP_N, OP_N, false>);
+  FEAST_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, NT, 0));
   const int r = std::max(1, cus * std::max(1, per_cu));
   if (c) c->store(r);
   return r;
@@ -773,7 +774,7 @@ int zgemm_resident_tiles() {
 int zgemm_kchunks(int M, int N, int K) {
   if (M <= 0 || N <= 0 || K < 512) return 1;
   const long tiles = (long)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  const long slots = zgemm_resident_tiles();
+  const long slots = zgemm_resident_tiles(g_z3m);
   // Cost model: rounds of resident workgroups times the K length each one runs.  A split
   // is taken only when it saves at least 3 % (the partial sums cost a pass over C).
   int best = 1;

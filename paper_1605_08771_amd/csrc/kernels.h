@@ -53,8 +53,8 @@ void cgemm(hipStream_t s, int opA, int opB, int M, int N, int K, zf alpha, const
            const zf* B, long ldb, zf beta, zf* C, long ldc, const Batch& bt = Batch());
 
 // K-chunk count for C = A B (FP64, op N/N; K = the inner length) that spreads the output
-// tiles of all chunks more evenly over the workgroups the device holds at once (1 = no
-// split; at most 8, chunks of at least 256).
+// tiles of all chunks more evenly over the workgroups the device holds at once of the kernel
+// the calling thread's product form selects (1 = no split; at most 8, chunks of at least 256).
 int zgemm_kchunks(int M, int N, int K);
 // C = A B (beta = 0).  nchunk > 1: partial products of K chunks into part
 // (nchunk * M * N elements, ld M), then summed into C in chunk order.
