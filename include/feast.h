@@ -211,6 +211,10 @@ typedef struct {
   int counted;             /* Ritz pairs that step 3 counted (the *m of the call) */
   double max_res;          /* largest residual over the counted pairs at the last iteration */
   double time_ms;          /* duration of the call on the handle's stream (HIP events) */
+  long long filter_columns; /* right-hand-side columns filtered in all: m0 per application,
+                               except that an application made for the filter-value test at
+                               what step 3 then finds to be the last iteration filters only
+                               the Ritz vectors inside I */
 } feast_solve_info;
 
 /* The step-3 decision of the last feast_solve / feast_solve_gen on h (Appendix, FEAST step 3;
@@ -259,7 +263,9 @@ int feast_solve_batched(feast_handle h, feast_dtype dt, int nprob, const feast_p
                         const feast_opts* opt, int nstreams);
 
 /* mu_k of the Ritz vectors returned by the last feast_solve with opt->spurious = 1 (host
- * array of m0 doubles).  Returns the number of values written. */
+ * array of m0 doubles).  When the last filter application covered only the Ritz vectors
+ * inside I (see filter_columns above), mu_k of the pairs outside I is the scalar filter
+ * rho(lambda_k).  Returns the number of values written. */
 int feast_get_filter_values(feast_handle h, double* mu, int m0);
 
 /* Phase timings of the last feast_solve / feast_filter_apply / feast_rayleigh_ritz call, in

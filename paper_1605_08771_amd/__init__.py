@@ -40,7 +40,7 @@ class FeastOpts(ctypes.Structure):
 class FeastSolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("filter_applications", ctypes.c_int),
                 ("counted", ctypes.c_int), ("max_res", ctypes.c_double),
-                ("time_ms", ctypes.c_double)]
+                ("time_ms", ctypes.c_double), ("filter_columns", ctypes.c_longlong)]
 
 
 class FeastProblem(ctypes.Structure):
@@ -297,6 +297,7 @@ class Feast:
         lib().feast_get_solve_info(self.h, ctypes.byref(info), counted.ctypes.data_as(_ip), m0)
         out["counted"] = np.flatnonzero(counted)
         out["filter_applications"] = info.filter_applications
+        out["filter_columns"] = info.filter_columns
         out["time_ms"] = info.time_ms
 
     def filter_apply_gen(self, A, B, X, emin, emax, n_c, Q=None):
@@ -401,7 +402,8 @@ class Feast:
                                         nstreams)
         results = [dict(status=st.value, X=X, lam=lam, res=res, m=m.value, iters=it.value,
                         mu=mu, counted=np.flatnonzero(counted), trace=trace[: it.value],
-                        filter_applications=info.filter_applications, time_ms=info.time_ms)
+                        filter_applications=info.filter_applications,
+                        filter_columns=info.filter_columns, time_ms=info.time_ms)
                    for (X, lam, res, m, it, st, mu, counted, trace, info) in outs]
         return bad, results
 

@@ -292,6 +292,7 @@ struct feast_ctx {
   // outcome of the last solve: step 3's counted pairs, filter applications, iterations
   std::vector<int> counted;
   int last_filters = 0, last_iters = 0, last_count = 0;
+  long long last_filter_cols = 0;  // right-hand-side columns filtered by the last solve
   double last_max_res = 0;
   PhaseTimer timer;
   KernelProfiler prof;
@@ -460,9 +461,10 @@ struct RitzInfo {
 // entry no longer falls below 0.9 of the previous one (it has reached its FP64 floor).
 int filter_core(feast_ctx* h, int dt, int n, int m0, const zd* X, long ldx, zd* Q, long ldq,
                 const zd* A = nullptr, long lda = 0, const RitzInfo* ritz = nullptr,
-                int refine = 0, bool adaptive = false) {
+                int refine = 0, bool adaptive = false, bool count = true) {
   hipStream_t s = h->stream;
-  h->last_filters++;
+  if (count) h->last_filters++;  // false: more columns of an application already counted
+  h->last_filter_cols += m0;
   const int np = h->f_np, nc = h->f_nc, nbt = h->f_nbt;
   const int sides = (dt == FEAST_C128) ? 2 : 1;
   const size_t blk = (size_t)nc * sides * np * m0;
@@ -1238,6 +1240,7 @@ int solve_impl(feast_handle h, feast_dtype dt, int n, const void* A, int lda, co
   const int m0 = opt->m0;
   h->counted.assign(m0, 0);
   h->last_filters = h->last_iters = h->last_count = 0;
+  h->last_filter_cols = 0;
   h->last_max_res = 0;
   try {
     hipStream_t s = h->stream;
@@ -1297,18 +1300,40 @@ int solve_impl(feast_handle h, feast_dtype dt, int n, const void* A, int lda, co
       }
       const bool plain = spur && plain_step3_converged(lambda, res, m0, emin, emax, opt->tol,
                                                        m0, it);
+      bool partial = false;  // this application has filtered columns [plo, phi) only
+      int plo = 0, phi = m0;
+      const zd* bxp = nullptr;
       if (plain) {
         scalar_filter_mu(h, (const double*)h->b_lam.p, m0);
       } else if (spur) {  // the next step 1 gives mu_k = Re(x_k^H rho(A) x_k)
         const zd* bx = rhs(Xw);
-        fs = filter_core(h, dt, n, m0, bx, n, Qf, n, Ac, ldac, mixed ? &ri : nullptr);
+        // Step 3 reads mu_k only for the Ritz pairs inside I (indices [lo, hi): lambda is in
+        // ascending order).  When every pair counted at the previous iteration now has a
+        // residual at or below tol, this application is likely the last one: filter those
+        // columns first, and the others only if step 3 does not stop.  Every column of an
+        // application is filtered independently, so the result is the same either way.
+        int lo = 0, hi = m0, conv = 0;
+        while (lo < m0 && !(lambda[lo] > emin)) ++lo;
+        hi = lo;
+        while (hi < m0 && lambda[hi] < emax) conv += (res[hi++] <= opt->tol);
+        partial = prev_m > 0 && conv >= prev_m && hi > lo && hi - lo < m0;
+        plo = lo;
+        phi = hi;
+        bxp = bx;
+        const int c0 = partial ? lo : 0, nc0 = partial ? hi - lo : m0;
+        RitzInfo rs0{mixed ? Reig + (size_t)c0 * n : nullptr, ri.lam ? ri.lam + c0 : nullptr};
+        fs = filter_core(h, dt, n, nc0, bx + (size_t)c0 * n, n, Qf + (size_t)c0 * n, n, Ac, ldac,
+                         mixed ? &rs0 : nullptr);
         if (fs) {
           st = fs;
           break;
         }
+        // outside [lo, hi) a partial application leaves the scalar filter rho(lambda_k)
+        if (partial) scalar_filter_mu(h, (const double*)h->b_lam.p, m0);
         double* dmu = h->b_mu.get<double>(m0);
-        coldot_re(s, bx, n, Qf, n, n, m0, dmu);
-        FEAST_HIP(hipMemcpyAsync(h->mu.data(), dmu, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
+        coldot_re(s, bx + (size_t)c0 * n, n, Qf + (size_t)c0 * n, n, n, nc0, dmu);
+        FEAST_HIP(hipMemcpyAsync(h->mu.data() + c0, dmu, sizeof(double) * nc0,
+                                 hipMemcpyDeviceToHost, s));
         FEAST_HIP(hipStreamSynchronize(s));
       }
       finish_timing(h);
@@ -1338,6 +1363,19 @@ int solve_impl(feast_handle h, feast_dtype dt, int n, const void* A, int lda, co
         break;
       }
       prev_m = mm;
+      if (partial) {  // step 3 did not stop: the other columns of this application
+        for (int part = 0; part < 2 && fs == 0; ++part) {
+          const int c0 = part ? phi : 0, ncol = part ? m0 - phi : plo;
+          if (ncol <= 0) continue;
+          RitzInfo rs1{mixed ? Reig + (size_t)c0 * n : nullptr, ri.lam ? ri.lam + c0 : nullptr};
+          fs = filter_core(h, dt, n, ncol, bxp + (size_t)c0 * n, n, Qf + (size_t)c0 * n, n, Ac,
+                           ldac, mixed ? &rs1 : nullptr, 0, false, false);
+        }
+        if (fs) {
+          st = fs;
+          break;
+        }
+      }
       if (!spur && it < opt->max_iter) {
         fs = filter_core(h, dt, n, m0, rhs(Xw), n, Qf, n, Ac, ldac,
                          mixed ? &ri : nullptr);  // step 1 of the next iteration
@@ -1560,6 +1598,7 @@ int feast_get_solve_info(feast_handle h, feast_solve_info* info, int* counted, i
   if (info) {
     info->iters = h->last_iters;
     info->filter_applications = h->last_filters;
+    info->filter_columns = h->last_filter_cols;
     info->counted = h->last_count;
     info->max_res = h->last_max_res;
     info->time_ms = h->timer.ms[P_TOTAL];

@@ -266,9 +266,37 @@ def test_solve_info_argument_checks():
     L = fm.lib()
     info = fm.FeastSolveInfo()
     assert L.feast_get_solve_info(None, ctypes.byref(info), None, 0) == -1
-    # the binding's structures have the C layout of include/feast.h (LP64: 136 and 32 bytes)
+    # the binding's structures have the C layout of include/feast.h (LP64: 136 and 40 bytes)
     assert ctypes.sizeof(fm.FeastProblem) == 136
-    assert ctypes.sizeof(fm.FeastSolveInfo) == 32
+    assert ctypes.sizeof(fm.FeastSolveInfo) == 40
+    _check_layout_against_header(fm.FeastSolveInfo, "feast_solve_info")
+    _check_layout_against_header(fm.FeastProblem, "feast_problem")
+
+
+def _check_layout_against_header(cls, cname):
+    """Sizes and field offsets of a binding structure equal those a C compiler gives the
+    declaration in include/feast.h."""
+    import os
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    names = [f[0] for f in cls._fields_]
+    # a trailing underscore marks a C member named like a Python keyword (lambda)
+    body = "".join(f'  printf("%zu\\n", offsetof({cname}, {n.rstrip("_")}));\n' for n in names)
+    src = ("#include <stddef.h>\n#include <stdio.h>\n#include \"feast.h\"\nint main(void) {\n"
+           f'  printf("%zu\\n", sizeof({cname}));\n' + body + "  return 0;\n}\n")
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        open(c, "w").write(src)
+        subprocess.run([cc, "-I", inc, c, "-o", exe], check=True, capture_output=True)
+        got = [int(v) for v in subprocess.run([exe], check=True, capture_output=True,
+                                               text=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(cls)
+    assert got[1:] == [getattr(cls, n).offset for n in names]
 
 
 def test_binding_refuses_mismatched_tensors():

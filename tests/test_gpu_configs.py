@@ -51,6 +51,9 @@ def test_c5_mixed_solve_full_size(fe):
         _check_converged(p, out, 1e-10)
         assert len(out["trace"]) == out["iters"] and out["trace"][-1] <= 1e-10
         assert out["filter_applications"] in (out["iters"], out["iters"] + 1)
+        fa, fc = out["filter_applications"], out["filter_columns"]
+        n_in = int(np.sum((out["lam"] > p.emin) & (out["lam"] < p.emax)))
+        assert fc in (fa * p.m0, (fa - 1) * p.m0 + n_in), (fa, fc, n_in)
     finally:
         del p, out
         torch.cuda.empty_cache()

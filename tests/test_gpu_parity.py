@@ -254,6 +254,12 @@ def test_solve_spurious_pairs_vs_oracle(fe, orc):
     np.testing.assert_allclose(out["mu"][kg], ref["mu"][ko], rtol=0, atol=1e-8)
     assert sin_theta_max(ref["X"][:, ko], out["X"].cpu().numpy()[:, kg]) < 1e-8
     assert abs(out["iters"] - ref["iters"]) <= 3
+    # every application filters all m0 columns, except that the last one, made for the
+    # filter-value test of what step 3 then found to be the last iteration, may cover only
+    # the Ritz vectors inside I
+    fa, fc = out["filter_applications"], out["filter_columns"]
+    n_in = int(np.sum((out["lam"] > p.emin) & (out["lam"] < p.emax)))
+    assert fc in (fa * p.m0, (fa - 1) * p.m0 + n_in), (fa, fc, n_in)
 
 
 # ---------------------------------------------------------------- mixed precision (FP32 factors)
