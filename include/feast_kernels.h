@@ -60,6 +60,16 @@ int feast_kern_sweeps(int prec, int n, int nc, int m0, int sides, const void* LU
  * solve is running.  Returns 0, or -1 for any other nbt (the setting is then unchanged). */
 int feast_tune_sweep_block(int nbt);
 
+/* Test hook for the filter application that a FEAST iteration with the filter-value test on
+ * makes after Rayleigh-Ritz (Appendix FEAST step 3 reads mu_k only inside I).  mode 0 (the
+ * default): when every pair counted at the previous iteration now has a residual at most
+ * tol, the Ritz vectors inside I are filtered first and the other columns only if step 3 does
+ * not stop; mode 1: that split is made at every such application.  Each column is filtered
+ * on its own, so both modes give the same iterates; mode 1 exists to exercise the second
+ * half of the split.  Process-wide: set it only while no solve is running.  Returns 0, or -1
+ * for any other mode (the setting is then unchanged). */
+int feast_tune_split_filter(int mode);
+
 /* Parallel-order two-sided Jacobi eigendecomposition of a Hermitian m x m matrix H
  * (ld m, complex128, not modified): the reduced eigenproblem of the Appendix, step 2.i.
  * d: device m doubles (eigenvalues ascending); W: device m x m eigenvectors (ld m).

@@ -114,6 +114,7 @@ def lib():
         L.feast_kern_lu.argtypes = [ci, _vp, ci, ci, ci, _dp, _vp, _ip, _ip, _vp]
         L.feast_kern_jacobi.argtypes = [_vp, ci, _vp, _vp, _vp]
         L.feast_tune_sweep_block.argtypes = [ci]
+        L.feast_tune_split_filter.argtypes = [ci]
         L.feast_kern_sweeps.argtypes = [ci, ci, ci, ci, ci, _vp, _vp, _vp, ci, _vp, _vp, _ip,
                                         _ip, _vp]
         _lib = L
@@ -126,6 +127,15 @@ def tune_sweep_block(nbt):
     st = lib().feast_tune_sweep_block(int(nbt))
     if st != 0:
         raise ValueError(f"sweep block height must be 0, 64, 128, 256 or 512, not {nbt}")
+
+
+def tune_split_filter(mode):
+    """Process-wide test hook: 1 splits every filter application made for the filter-value
+    test into the Ritz vectors inside I and the rest (0, the default: only at a likely last
+    iteration).  Both give the same iterates.  Set it only while no solve is running."""
+    st = lib().feast_tune_split_filter(int(mode))
+    if st != 0:
+        raise ValueError(f"split-filter mode must be 0 or 1, not {mode}")
 
 
 def fortran(t):

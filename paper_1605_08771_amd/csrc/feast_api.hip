@@ -144,6 +144,11 @@ struct EventPool {
 // expanded-subspace methods; a solve that needs more than this reports FEAST_EIG_FAILED.
 constexpr int kJacobiMaxSweeps = 60;
 
+// 1: every filter application made for the filter-value test filters the Ritz vectors inside
+// I first and the other columns after step 3 (a test hook for that path); 0: only when the
+// iteration is likely the last.
+std::atomic<int> g_split_filter{0};
+
 constexpr int NCLASS = 6;
 enum { K_LU = 0, K_SOLVE = 1, K_RR = 2, K_REFINE = 3, K_OTHER = 4, K_EIG = 5 };
 
@@ -1316,7 +1321,9 @@ int solve_impl(feast_handle h, feast_dtype dt, int n, const void* A, int lda, co
         while (lo < m0 && !(lambda[lo] > emin)) ++lo;
         hi = lo;
         while (hi < m0 && lambda[hi] < emax) conv += (res[hi++] <= opt->tol);
-        partial = prev_m > 0 && conv >= prev_m && hi > lo && hi - lo < m0;
+        partial = (g_split_filter.load(std::memory_order_relaxed) != 0 ||
+                   (prev_m > 0 && conv >= prev_m)) &&
+                  hi > lo && hi - lo < m0;
         plo = lo;
         phi = hi;
         bxp = bx;
@@ -1606,6 +1613,12 @@ int feast_get_solve_info(feast_handle h, feast_solve_info* info, int* counted, i
   if (counted)
     for (int k = 0; k < m0; ++k) counted[k] = k < (int)h->counted.size() ? h->counted[k] : 0;
   return h->last_count;
+}
+
+int feast_tune_split_filter(int mode) {
+  if (mode != 0 && mode != 1) return -1;
+  g_split_filter.store(mode);
+  return 0;
 }
 
 int feast_get_filter_values(feast_handle h, double* mu, int m0) {

@@ -182,6 +182,18 @@ def test_kern_sweeps_argument_checks_and_shape_query():
                                None) == -7
 
 
+def test_split_filter_hook_argument_checks():
+    """The split-filter test hook takes 0 or 1 and rejects anything else unchanged."""
+    L = fm.lib()
+    try:
+        assert L.feast_tune_split_filter(2) == -1 and L.feast_tune_split_filter(-1) == -1
+        assert L.feast_tune_split_filter(1) == 0
+        with pytest.raises(ValueError):
+            fm.tune_split_filter(3)
+    finally:
+        assert L.feast_tune_split_filter(0) == 0
+
+
 def test_sweep_block_override():
     """The tuning hook: heights 64..512 change the padding the factorizations use; 0 restores
     the table; anything else is rejected and leaves the setting alone."""

@@ -262,6 +262,43 @@ def test_solve_spurious_pairs_vs_oracle(fe, orc):
     assert fc in (fa * p.m0, (fa - 1) * p.m0 + n_in), (fa, fc, n_in)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_split_filter_applications_give_the_same_iterates(fe, prec):
+    """The filter application made for the filter-value test may filter the Ritz vectors inside
+    I and the other columns in two calls.  Forcing that split at every such application (the
+    test hook) must give bit-identical iterates, mu values inside I and column counts to the
+    default schedule, which splits only at a likely last iteration (FP64 and FP32 factors)."""
+    import torch
+    import paper_1605_08771_amd as fm
+    p = gen.config2(n=500, seed_tag=79, n_in=30, n_in_edge=6, n_out_edge=30, m0=50, n_c=8,
+                    max_iter=150)
+    kw = dict(n_c=8, tol=1e-12, max_iter=150, anorm=p.anorm, spurious=True, prec=prec,
+              refine_max=0)
+    outs = []
+    for mode in (0, 1):
+        fm.tune_split_filter(mode)
+        try:
+            fe.invalidate()
+            o = fe.solve(_dev(p.A), p.emin, p.emax, p.m0, X0=_dev(p.X0), **kw)
+            torch.cuda.synchronize()
+        finally:
+            fm.tune_split_filter(0)
+        o["X"] = o["X"].cpu().numpy()
+        outs.append(o)
+    fe.invalidate()
+    a, b = outs
+    assert a["status"] == b["status"] == 0 and a["m"] == b["m"] == p.m_true
+    assert a["iters"] == b["iters"] and a["filter_applications"] == b["filter_applications"]
+    assert a["filter_columns"] == b["filter_columns"]
+    for k in ("lam", "res", "X", "counted"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    inside = (a["lam"] > p.emin) & (a["lam"] < p.emax)
+    np.testing.assert_array_equal(a["mu"][inside], b["mu"][inside])
+    n_in = int(np.sum(inside))
+    fa = a["filter_applications"]
+    assert a["filter_columns"] in (fa * p.m0, (fa - 1) * p.m0 + n_in)
+
+
 # ---------------------------------------------------------------- mixed precision (FP32 factors)
 # fp32: FP32 matrix-core products; bf16x3: the same FP32 factor storage and refinement with the
 # factorization's and the solves' matrix-core products split into bf16 hi + lo parts.
