@@ -50,8 +50,8 @@ DEFAULT_PREC = {"c1": "fp64", "c2": "fp64", "c3": "fp32ir", "c4": "fp32ir", "c5"
 # height table (sweep_tune.h) and their common header hash to the version the counters were
 # taken on.
 SWEEP_TRAFFIC = {
-    ("c2", "fp64"): {"sources": "b30deb2023fed045", "bytes_per_launch": 1.286e9},
-    ("c5", "fp32ir"): {"sources": "b30deb2023fed045", "bytes_per_launch": 3.677e9},
+    ("c2", "fp64"): {"sources": "f3d143e28158b223", "bytes_per_launch": 1.286e9},
+    ("c5", "fp32ir"): {"sources": "f3d143e28158b223", "bytes_per_launch": 3.677e9},
 }
 
 

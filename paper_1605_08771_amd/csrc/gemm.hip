@@ -561,7 +561,7 @@ __device__ __forceinline__ void gemmx_tile(const Args<float2>& a, int prob, int 
       }                                                                                  \
   }
 
-  // prefetch distance two, as in gemm_tile
+  // prefetch distance two: the loads of K-tile kt+2 are in flight while kt is multiplied
   const int nkt = (K + XBK - 1) / XBK;
   if (nkt > 0) {
     FEAST_XLOAD(0, pa, pb)
